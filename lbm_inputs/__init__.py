@@ -1,0 +1,88 @@
+"""Seeded synthetic workloads for the porous-convection lattice Boltzmann step.
+
+This module holds workload recipes (geometry, parameters, wall rules, seeds)
+and seeded random population states.  It contains none of the method's
+arithmetic: no equilibria, no matrices, no parameter mapping.  Both the
+product library's binding and the FP64 oracle receive the same plain dict.
+
+The workloads stand in for the paper's own test problems (there is no dataset):
+the cubic porous cavity of Sec. 4.2 (hot and cold x-walls, adiabatic side
+walls, buoyancy along z) and channels like those of Sec. 4.1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def face(flow: str, heat: str, T_wall: float = 0.0, u_wall=(0.0, 0.0, 0.0)) -> dict:
+    return {"flow": flow, "heat": heat, "T_wall": float(T_wall),
+            "u_wall": tuple(float(v) for v in u_wall)}
+
+
+def cavity(n, *, lattice=19, porosity=0.6, darcy=1e-2, rayleigh=1e4, prandtl=1.0,
+           seed=1, noise_amp=1e-3, T_hot=0.5, T_cold=-0.5, forchheimer=1.0,
+           mach=0.1, **extra) -> dict:
+    """Natural convection in a porous box: isothermal -x (hot) and +x (cold)
+    walls, the other four adiabatic, bounce-back everywhere, buoyancy along +z.
+    Initial state: rest, T linear between the walls plus seeded uniform noise.
+    ``n`` is an edge length or an (nx, ny, nz) tuple; L = nx."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    wl = {
+        "nx": int(nx), "ny": int(ny), "nz": int(nz), "q": int(lattice),
+        "porosity": float(porosity), "darcy": float(darcy),
+        "rayleigh": float(rayleigh), "prandtl": float(prandtl),
+        "mach": float(mach), "forchheimer": float(forchheimer),
+        "gravity_axis": 2, "length_axis": 0,
+        "T_ref": 0.5 * (T_hot + T_cold), "delta_T": float(T_hot - T_cold),
+        "faces": [face("wall", "isothermal", T_hot), face("wall", "isothermal", T_cold),
+                  face("wall", "adiabatic"), face("wall", "adiabatic"),
+                  face("wall", "adiabatic"), face("wall", "adiabatic")],
+        "init_axis": 0, "init_T_lo": float(T_hot), "init_T_hi": float(T_cold),
+        "seed": int(seed), "noise_amp": float(noise_amp),
+    }
+    wl.update(extra)
+    return wl
+
+
+def config_cavity_fp64() -> dict:
+    """32^3 porous cavity, D3Q19 + D3Q7, FP64: phi 0.6, Da 1e-2, Ra 1e4, Pr 1,
+    2000 steps, seed 1."""
+    wl = cavity(32, porosity=0.6, darcy=1e-2, rayleigh=1e4, prandtl=1.0, seed=1)
+    wl.update(name="cavity32_fp64", precision="fp64", steps=2000)
+    return wl
+
+
+def config_cavity_fp32() -> dict:
+    """256^3 porous cavity, D3Q19 + D3Q7, FP32: phi 0.4, Da 1e-4, Ra 1e6, Pr 1,
+    seed 2 (20000 steps in the full run)."""
+    wl = cavity(256, porosity=0.4, darcy=1e-4, rayleigh=1e6, prandtl=1.0, seed=2)
+    wl.update(name="cavity256_fp32", precision="fp32", steps=20000)
+    return wl
+
+
+def periodic_box(shape, *, lattice=19, **extra) -> dict:
+    """Fully periodic box with default Sec. 4 rates (no walls)."""
+    nx, ny, nz = shape
+    wl = {
+        "nx": nx, "ny": ny, "nz": nz, "q": lattice,
+        "porosity": 0.7, "darcy": 1e-2, "rayleigh": 1e4, "prandtl": 1.0,
+        "gravity_axis": 2, "length_axis": 0, "T_ref": 0.0, "delta_T": 1.0,
+        "faces": [face("periodic", "periodic")] * 6,
+        "init_axis": -1, "seed": 7, "noise_amp": 1e-2,
+    }
+    wl.update(extra)
+    return wl
+
+
+def random_state(q: int, shape, seed: int, *, f_base=None, amp=0.05, T_amp=0.5):
+    """Seeded random pre-collision populations.  f_i = base * (1 + amp U(-1,1)),
+    g_k = (T_amp U(-1,1)) / 7 + small noise.  The values are arbitrary positive
+    (f) or signed (g) numbers, not equilibria; ``f_base`` defaults to 1/q."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    base = (1.0 / q) if f_base is None else f_base
+    f = base * (1.0 + amp * rng.uniform(-1.0, 1.0, size=(q, nz, ny, nx)))
+    T = T_amp * rng.uniform(-1.0, 1.0, size=(nz, ny, nx))
+    g = np.broadcast_to(T / 7.0, (7, nz, ny, nx)) * (1.0 + amp * rng.uniform(
+        -1.0, 1.0, size=(7, nz, ny, nx)))
+    return np.ascontiguousarray(f), np.ascontiguousarray(g)
