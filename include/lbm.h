@@ -1,0 +1,199 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) implementation of the fused time step of
+ * the REV-scale double-distribution-function MRT lattice Boltzmann model of
+ * Liu & He, "Three-dimensional multiple-relaxation-time lattice Boltzmann
+ * model for convection heat transfer in porous media at the REV scale"
+ * (arXiv:1611.03329).
+ *
+ * One lattice = one box of nx*ny*nz fluid nodes carrying
+ *   - density populations f_i, D3Q19 (Sec. 3.1.2) or D3Q15 (Sec. 3.1.1), and
+ *   - temperature populations g_k, D3Q7 (Sec. 3.2).
+ * One time step, for every node, fuses (all on the GPU):
+ *   streaming of f (Eq. 10) and g (Eq. 35) with the wall rules below;
+ *   rho (Eq. 25), sigma*T (Eq. 39), buoyancy G (Eq. 5), the explicit velocity
+ *   closure (Eqs. 27-28), the porous total force F (Eq. 4);
+ *   the flow collision in moment space (Eq. 9) with the porosity-dependent
+ *   equilibria (Eq. 21 / 15), the forcing moments (Eq. 23 / 17) and the
+ *   relaxation rates (Eq. 22 / 16);
+ *   the temperature collision in moment space (Eq. 34) with Eqs. 36-38, 43.
+ *
+ * Conventions
+ *   - lattice units rho0 = dt = dx = c = 1 (Sec. 4), cs^2 = 1/3, csT^2 = varpi/3;
+ *   - node (x,y,z), x fastest; linear index n = x + nx*(y + ny*z);
+ *   - non-periodic faces are halfway walls at -1/2 and n-1/2 (L = n along
+ *     length_axis, K = Da*L^2);
+ *   - time t counts completed steps; the state at time t is the pre-collision
+ *     populations f(t), g(t); fields, Nusselt numbers and totals at time t
+ *     are computed from that state;
+ *   - walls: halfway bounce-back for f (plus 2 w_i rho0 e_i.u_w / cs^2 for a
+ *     moving wall), anti-bounce-back for an isothermal g
+ *     (g_k = -g*_kbar + 2 omega_k sigma T_w), bounce-back for an adiabatic g.
+ *     (The paper used non-equilibrium extrapolation, Sec. 4; these wall rules
+ *     are a deliberate substitution.)  A link leaving through two wall faces
+ *     takes the wall velocity of the first of them in face order.
+ *
+ * Threading and streams: a lattice is not thread-safe; all of its device work
+ * is enqueued on the HIP stream given at creation (or lbm_set_stream).
+ * Functions documented as "asynchronous" return after enqueueing; functions
+ * that return host values synchronize that stream.
+ *
+ * Errors: every function returns an lbm_status; LBM_OK is 0.  On an error the
+ * lattice is unchanged unless stated; lbm_last_error() returns a thread-local
+ * message describing the last failure on the calling thread.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_lattice lbm_lattice; /* opaque */
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_INVALID_ARG = 1,   /* bad parameter, size or pointer */
+  LBM_ERR_OUT_OF_MEMORY = 2, /* device allocation failed or caller buffer too small */
+  LBM_ERR_DEVICE = 3,        /* a HIP call failed */
+  LBM_ERR_UNSTABLE = 4,      /* a check found a non-finite value or |u| > 0.5 (sticky) */
+  LBM_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
+} lbm_status;
+
+typedef enum {
+  LBM_FP64 = 0, /* populations stored and computed in FP64 */
+  LBM_FP32 = 1  /* populations stored and computed in FP32 (stored shifted by rest weights) */
+} lbm_precision;
+
+typedef enum { LBM_FLOW_PERIODIC = 0, LBM_FLOW_WALL = 1 } lbm_flow_bc;
+typedef enum { LBM_HEAT_PERIODIC = 0, LBM_HEAT_ADIABATIC = 1, LBM_HEAT_ISOTHERMAL = 2 } lbm_heat_bc;
+
+/* One face of the box.  Face order: 0 = -x, 1 = +x, 2 = -y, 3 = +y, 4 = -z, 5 = +z.
+ * Opposite faces are both periodic (flow and heat) or both not. */
+typedef struct {
+  int32_t flow;      /* lbm_flow_bc */
+  int32_t heat;      /* lbm_heat_bc */
+  double T_wall;     /* isothermal wall temperature */
+  double u_wall[3];  /* wall velocity of a WALL face (moving-wall bounce-back) */
+} lbm_face;
+
+/* Lattice description.  Fill with lbm_default_params() first (Sec. 4 defaults:
+ * sigma = J = Gamma = 1, varpi = 1/2, s_rho = s_j = 1, s_e = s_eps = s_q = s_pi = 1.1,
+ * s_m = 1.2, zeta_T = 1, zeta_e = zeta_nu = 1.2, Ma = 0.1). */
+typedef struct {
+  int32_t nx, ny, nz;     /* fluid nodes per axis, >= 1 */
+  int32_t lattice;        /* 19 (D3Q19) or 15 (D3Q15) */
+  int32_t precision;      /* lbm_precision */
+  double porosity;        /* phi in (0,1] (Eqs. 2, 4) */
+  double darcy;           /* Da = K/L^2 > 0 (Eq. 7) */
+  double rayleigh;        /* Ra >= 0 (Eq. 7); sets g*beta = Ra nu alpha / (L^3 delta_T) */
+  double prandtl;         /* Pr = nu/alpha > 0 (Eq. 7) */
+  double reynolds;        /* > 0 selects the channel mapping of Eq. 51: nu = u_char L / Re */
+  double u_char;          /* characteristic speed of the channel mapping */
+  double mach;            /* Ma of the cavity mapping (Eq. 56) */
+  double forchheimer;     /* multiplier of F_phi of Eq. 6 (1: generalized non-Darcy, 0: Brinkman) */
+  double sigma, J, Gamma, varpi;  /* Eqs. 3, 7, 37 */
+  double s_rho, s_e, s_eps, s_j, s_q, s_pi, s_m; /* Eqs. 16, 22 (s_pi unused by D3Q15) */
+  double zeta_T, zeta_e, zeta_nu;                /* Eq. 38 */
+  double s_nu_set;        /* > 0: use as s_nu instead of Eq. 56 / 51 */
+  double zeta_alpha_set;  /* > 0: use as zeta_alpha instead of Eq. 56 / 51 */
+  int32_t gravity_axis;   /* buoyancy acts along +axis: G_axis += g*beta*(T - T_ref) (Eq. 5) */
+  int32_t length_axis;    /* L = node count along this axis */
+  double T_ref;           /* T0 of Eq. 5; also the storage shift of g */
+  double delta_T;         /* temperature scale of Ra and of the Nusselt numbers, > 0 */
+  double accel[3];        /* constant external acceleration a of Eq. 5 */
+  lbm_face face[6];
+  int32_t init_axis;      /* initial T: -1 uniform T_ref, else linear along this axis ... */
+  double init_T_lo;       /* ... from init_T_lo at the -1/2 face to init_T_hi at n-1/2 ... */
+  double init_T_hi;
+  uint64_t seed;          /* ... plus noise_amp*(2r-1), r = (SplitMix64(seed ^ n) >> 11) * 2^-53 */
+  double noise_amp;
+  int32_t check_interval; /* K > 0: residual check at every multiple of K steps; 0 disables */
+} lbm_params;
+
+/* Derived quantities (Eqs. 6, 7, 28, 32, 41, 51, 56). */
+typedef struct {
+  double L, s_nu, zeta_alpha, nu_e, nu, alpha_e, alpha, K, F_phi, gbeta, l0, l1;
+} lbm_derived;
+
+/* Fills *p with the defaults above and an 8^3 D3Q19 FP64 box with all six faces
+ * adiabatic no-slip walls.  Never fails for non-NULL p. */
+void lbm_default_params(lbm_params* p);
+
+/* Device bytes a lattice with these parameters needs (state, check snapshot,
+ * reduction scratch).  Returns LBM_ERR_INVALID_ARG / LBM_ERR_UNSUPPORTED for
+ * parameters lbm_create would reject; *bytes is 0 then. */
+lbm_status lbm_required_bytes(const lbm_params* p, size_t* bytes);
+
+/* Creates a lattice and enqueues its initialisation (f = f^eq(rho0, 0) of Eq. 24/18,
+ * g = g^eq(T_init, 0) of Eq. 42) on `stream` (a hipStream_t; NULL = null stream).
+ * dev_buf: caller-owned device memory of at least lbm_required_bytes() bytes,
+ * 256-byte aligned, kept alive until lbm_destroy; or NULL, in which case the
+ * library allocates (and later frees) it.  Parameters are validated before any
+ * allocation or device work.  Asynchronous. */
+lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t bytes, void* stream,
+                      lbm_lattice** out);
+
+/* Waits for the lattice's stream, frees what the library allocated (never the
+ * caller's buffer) and the handle.  NULL is accepted. */
+lbm_status lbm_destroy(lbm_lattice* h);
+
+/* Changes the stream later calls enqueue on. The caller orders the two streams. */
+lbm_status lbm_set_stream(lbm_lattice* h, void* stream);
+
+/* Enqueues nsteps >= 0 fused time steps t -> t + nsteps.  When check_interval
+ * K > 0 the steps that start at times n-1 and n (n a positive multiple of K)
+ * also compute the residual r(n) (see lbm_residual).  Asynchronous; returns
+ * LBM_ERR_UNSTABLE without enqueueing if an earlier check already found the
+ * lattice unstable. */
+lbm_status lbm_step(lbm_lattice* h, int64_t nsteps);
+
+/* Current time t (completed steps).  Host-only, no synchronization. */
+lbm_status lbm_time(const lbm_lattice* h, int64_t* t);
+
+lbm_status lbm_derived_params(const lbm_lattice* h, lbm_derived* d);
+
+/* Writes rho (Eq. 25), u (Eqs. 27-28) and T (Eq. 39) at the current time into
+ * caller-owned DEVICE buffers of nx*ny*nz FP64 values each, x fastest.  Any
+ * pointer may be NULL to skip that field.  Asynchronous. */
+lbm_status lbm_fields(lbm_lattice* h, double* rho, double* ux, double* uy, double* uz, double* T);
+
+/* Face Nusselt numbers at the current time, FP64, into host nu[6]: for every
+ * isothermal face, the mean over the face's nodes of the heat that entered the
+ * fluid through it during the last streaming (2 g_k - 2 omega_k sigma T_w for
+ * the incoming population k of anti-bounce-back), times L/(alpha_e delta_T):
+ * the midpoint rule for Nu_3D of Eqs. 53-55.  0 for other faces.  The hot wall
+ * of a cavity reports +Nu, the cold wall -Nu.  Synchronizes. */
+lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]);
+
+/* Most recent residual check: r(n) = max(|u(n) - u(n-1)|_2 / |u(n)|_2,
+ * |theta(n) - theta(n-1)|_2 / |theta(n)|_2), theta = (T - T_ref)/delta_T + 1/2,
+ * sums over all nodes in FP64 (a term whose denominator is 0 counts as 0 if
+ * its numerator is 0).  *at_step = n, or -1 (and *r = -1) if no check has run.
+ * Returns LBM_ERR_UNSTABLE if the check found the lattice unstable.
+ * Synchronizes. */
+lbm_status lbm_residual(lbm_lattice* h, double* r, int64_t* at_step);
+
+/* Sum over nodes of rho and of sigma*T at the current time, FP64 (two-pass,
+ * deterministic).  Synchronizes. */
+lbm_status lbm_totals(lbm_lattice* h, double* mass, double* heat);
+
+/* Copies the pre-collision state at the current time into caller-owned DEVICE
+ * buffers, FP64, layout [q][z][y][x] for f (q = 19 or 15) and [7][z][y][x] for g.
+ * Either pointer may be NULL.  Asynchronous. */
+lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g);
+
+/* Replaces the state with caller-given DEVICE FP64 arrays (same layout as
+ * lbm_get_state; both required), rounding to the storage precision.  The time
+ * counter is kept; the pending residual snapshot is discarded.  Asynchronous. */
+lbm_status lbm_set_state(lbm_lattice* h, const double* f, const double* g);
+
+const char* lbm_status_string(lbm_status s);
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

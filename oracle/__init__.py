@@ -111,6 +111,8 @@ def lib():
                                    ctypes.c_double, ctypes.c_double, _D]
         L.ref_total_force.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, _D]
+        L.ref_threads.argtypes = []
+        L.ref_threads.restype = ctypes.c_int
         L.ref_splitmix64.argtypes = [ctypes.c_uint64]
         L.ref_splitmix64.restype = ctypes.c_uint64
         L.ref_noise.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double]
@@ -204,6 +206,10 @@ def total_force(u, G, phi, nu, K, F_phi):
     _check(lib().ref_total_force(_ptr(_vec(u, 3)), _ptr(_vec(G, 3)), phi, nu, K, F_phi,
                                  _ptr(out)), "total_force")
     return out
+
+
+def threads() -> int:
+    return int(lib().ref_threads())
 
 
 def splitmix64(state: int) -> int:

@@ -34,6 +34,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---------------------------------------------------------------- lattices */
 
@@ -359,6 +362,14 @@ int ref_total_force(const double* u, const double* G, double phi, double nu, dou
 }
 
 /* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): one output from state s */
+int ref_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 uint64_t ref_splitmix64(uint64_t s) {
   uint64_t z = s + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

@@ -130,6 +130,8 @@ int ref_velocity(int q, const double* f, const double* G, double phi, double nu,
 /* total force (Eq. 4) */
 int ref_total_force(const double* u, const double* G, double phi, double nu, double K,
                     double F_phi, double* F);
+/* threads the time loop uses (OpenMP over nodes) */
+int ref_threads(void);
 /* SplitMix64 output for state (seed ^ n) and the uniform noise drawn from it */
 uint64_t ref_splitmix64(uint64_t state);
 double ref_noise(uint64_t seed, uint64_t n, double amp);

@@ -1,0 +1,260 @@
+"""ctypes binding of ``liblbm.so`` (the C ABI in include/lbm.h).
+
+Argument marshalling only: every step of the time loop, the fields, the
+Nusselt numbers, the residual and the totals are computed by the HIP kernels
+behind the C ABI.  PyTorch provides device memory and the stream.  There is no
+CPU fallback: if the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime that liblbm.so then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()' "
+        "or python paper_1611_03329_amd/build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FP64 = 0
+FP32 = 1
+PRECISIONS = {"fp64": FP64, "fp32": FP32}
+FLOW = {"periodic": 0, "wall": 1}
+HEAT = {"periodic": 0, "adiabatic": 1, "isothermal": 2}
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error",
+          4: "unstable", 5: "unsupported"}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class UnstableError(LBMError):
+    pass
+
+
+class Face(ctypes.Structure):
+    _fields_ = [("flow", ctypes.c_int32), ("heat", ctypes.c_int32),
+                ("T_wall", ctypes.c_double), ("u_wall", ctypes.c_double * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("lattice", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("porosity", ctypes.c_double), ("darcy", ctypes.c_double),
+        ("rayleigh", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("reynolds", ctypes.c_double), ("u_char", ctypes.c_double),
+        ("mach", ctypes.c_double), ("forchheimer", ctypes.c_double),
+        ("sigma", ctypes.c_double), ("J", ctypes.c_double),
+        ("Gamma", ctypes.c_double), ("varpi", ctypes.c_double),
+        ("s_rho", ctypes.c_double), ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double),
+        ("s_j", ctypes.c_double), ("s_q", ctypes.c_double), ("s_pi", ctypes.c_double),
+        ("s_m", ctypes.c_double),
+        ("zeta_T", ctypes.c_double), ("zeta_e", ctypes.c_double), ("zeta_nu", ctypes.c_double),
+        ("s_nu_set", ctypes.c_double), ("zeta_alpha_set", ctypes.c_double),
+        ("gravity_axis", ctypes.c_int32), ("length_axis", ctypes.c_int32),
+        ("T_ref", ctypes.c_double), ("delta_T", ctypes.c_double),
+        ("accel", ctypes.c_double * 3),
+        ("face", Face * 6),
+        ("init_axis", ctypes.c_int32),
+        ("init_T_lo", ctypes.c_double), ("init_T_hi", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
+        ("check_interval", ctypes.c_int32),
+    ]
+
+
+class Derived(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("L", "s_nu", "zeta_alpha", "nu_e", "nu", "alpha_e", "alpha", "K",
+                 "F_phi", "gbeta", "l0", "l1")]
+
+
+_P = ctypes.POINTER(Params)
+_V = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+_lib.lbm_default_params.argtypes = [_P]
+_lib.lbm_default_params.restype = None
+_lib.lbm_required_bytes.argtypes = [_P, ctypes.POINTER(ctypes.c_size_t)]
+_lib.lbm_create.argtypes = [_P, _V, ctypes.c_size_t, _V, ctypes.POINTER(_V)]
+_lib.lbm_destroy.argtypes = [_V]
+_lib.lbm_set_stream.argtypes = [_V, _V]
+_lib.lbm_step.argtypes = [_V, ctypes.c_int64]
+_lib.lbm_time.argtypes = [_V, _I64]
+_lib.lbm_derived_params.argtypes = [_V, ctypes.POINTER(Derived)]
+_lib.lbm_fields.argtypes = [_V, _V, _V, _V, _V, _V]
+_lib.lbm_nusselt.argtypes = [_V, _D]
+_lib.lbm_residual.argtypes = [_V, _D, _I64]
+_lib.lbm_totals.argtypes = [_V, _D, _D]
+_lib.lbm_get_state.argtypes = [_V, _V, _V]
+_lib.lbm_set_state.argtypes = [_V, _V, _V]
+_lib.lbm_status_string.argtypes = [ctypes.c_int]
+_lib.lbm_status_string.restype = ctypes.c_char_p
+_lib.lbm_last_error.argtypes = []
+_lib.lbm_last_error.restype = ctypes.c_char_p
+for _name in ("lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_step",
+              "lbm_time", "lbm_derived_params", "lbm_fields", "lbm_nusselt", "lbm_residual",
+              "lbm_totals", "lbm_get_state", "lbm_set_state"):
+    getattr(_lib, _name).restype = ctypes.c_int
+
+
+def library() -> ctypes.CDLL:
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = _lib.lbm_last_error().decode(errors="replace")
+        cls = UnstableError if status == 4 else LBMError
+        raise cls(status, msg)
+
+
+_SKIP_KEYS = {"name", "steps", "q"}
+
+
+def make_params(workload: dict, precision: str | int = "fp64", check_interval: int | None = None) -> Params:
+    """Fills the C parameter struct from a plain workload dict (lbm_inputs)."""
+    p = Params()
+    _lib.lbm_default_params(ctypes.byref(p))
+    for key, val in workload.items():
+        if key == "faces":
+            for k, fc in enumerate(val):
+                p.face[k].flow = FLOW[fc["flow"]]
+                p.face[k].heat = HEAT[fc["heat"]]
+                p.face[k].T_wall = float(fc.get("T_wall", 0.0))
+                for a in range(3):
+                    p.face[k].u_wall[a] = float(fc.get("u_wall", (0.0, 0.0, 0.0))[a])
+        elif key == "accel":
+            for a in range(3):
+                p.accel[a] = float(val[a])
+        elif key == "precision":
+            continue
+        elif key in _SKIP_KEYS:
+            continue
+        else:
+            if not hasattr(p, key):
+                raise KeyError(f"unknown workload key {key!r}")
+            setattr(p, key, val)
+    p.lattice = int(workload.get("lattice", workload.get("q", 19)))
+    prec = workload.get("precision", precision) if precision is None else precision
+    p.precision = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    if check_interval is not None:
+        p.check_interval = int(check_interval)
+    return p
+
+
+def required_bytes(params: Params) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.lbm_required_bytes(ctypes.byref(params), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _ptr(t) -> ctypes.c_void_p | None:
+    if t is None:
+        return None
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """One lattice on the current CUDA (HIP) device.  Device memory is a torch
+    uint8 tensor owned by this object; all work runs on ``stream``."""
+
+    def __init__(self, workload: dict, precision: str = "fp64", check_interval: int = 0,
+                 stream: torch.cuda.Stream | None = None, device=None):
+        self.params = make_params(workload, precision, check_interval)
+        self.q = int(self.params.lattice)
+        self.shape = (int(self.params.nz), int(self.params.ny), int(self.params.nx))
+        self.nodes = self.shape[0] * self.shape[1] * self.shape[2]
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.nbytes = required_bytes(self.params)
+        self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.buf.data_ptr()
+        self._base = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = ctypes.c_void_p()
+        _check(_lib.lbm_create(ctypes.byref(self.params), ctypes.c_void_p(self._base),
+                               ctypes.c_size_t(self.nbytes), ctypes.c_void_p(self.stream.cuda_stream),
+                               ctypes.byref(h)))
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.lbm_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- stepping
+    def step(self, n: int = 1):
+        _check(_lib.lbm_step(self._h, int(n)))
+
+    @property
+    def time(self) -> int:
+        t = ctypes.c_int64()
+        _check(_lib.lbm_time(self._h, ctypes.byref(t)))
+        return int(t.value)
+
+    def derived(self) -> dict:
+        d = Derived()
+        _check(_lib.lbm_derived_params(self._h, ctypes.byref(d)))
+        return {k: getattr(d, k) for k, _ in Derived._fields_}
+
+    # -- outputs
+    def fields(self) -> dict:
+        out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device)
+               for k in ("rho", "ux", "uy", "uz", "T")}
+        _check(_lib.lbm_fields(self._h, *(_ptr(out[k]) for k in ("rho", "ux", "uy", "uz", "T"))))
+        return out
+
+    def nusselt(self):
+        nu = (ctypes.c_double * 6)()
+        _check(_lib.lbm_nusselt(self._h, nu))
+        return [float(v) for v in nu]
+
+    def residual(self):
+        r = ctypes.c_double()
+        at = ctypes.c_int64()
+        _check(_lib.lbm_residual(self._h, ctypes.byref(r), ctypes.byref(at)))
+        return float(r.value), int(at.value)
+
+    def totals(self):
+        m = ctypes.c_double()
+        q = ctypes.c_double()
+        _check(_lib.lbm_totals(self._h, ctypes.byref(m), ctypes.byref(q)))
+        return float(m.value), float(q.value)
+
+    def get_state(self):
+        f = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
+        g = torch.empty((7,) + self.shape, dtype=torch.float64, device=self.device)
+        _check(_lib.lbm_get_state(self._h, _ptr(f), _ptr(g)))
+        return f, g
+
+    def set_state(self, f, g):
+        f = torch.as_tensor(f, dtype=torch.float64).to(self.device).contiguous()
+        g = torch.as_tensor(g, dtype=torch.float64).to(self.device).contiguous()
+        assert tuple(f.shape) == (self.q,) + self.shape and tuple(g.shape) == (7,) + self.shape
+        _check(_lib.lbm_set_state(self._h, _ptr(f), _ptr(g)))
+        # keep the inputs alive until the copy kernel has run
+        self.stream.synchronize()
