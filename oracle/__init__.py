@@ -23,8 +23,8 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FACE_NAMES = ("-x", "+x", "-y", "+y", "-z", "+z")
-FLOW = {"periodic": 0, "wall": 1}
-HEAT = {"periodic": 0, "adiabatic": 1, "isothermal": 2}
+FLOW = {"periodic": 0, "wall": 1, "outlet": 3}
+HEAT = {"periodic": 0, "adiabatic": 1, "isothermal": 2, "outflow": 3}
 
 
 def build(force: bool = True) -> str:
@@ -65,6 +65,7 @@ class _Params(ctypes.Structure):
         ("init_axis", ctypes.c_int32),
         ("init_T_lo", ctypes.c_double), ("init_T_hi", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
+        ("init_u", ctypes.c_double * 3),
     ]
 
 
@@ -232,9 +233,10 @@ def params_from_workload(wl: dict) -> _Params:
                 p.face[k].T_wall = float(fc.get("T_wall", 0.0))
                 for a in range(3):
                     p.face[k].u_wall[a] = float(fc.get("u_wall", (0.0, 0.0, 0.0))[a])
-        elif key == "accel":
+        elif key in ("accel", "init_u"):
+            arr = getattr(p, key)
             for a in range(3):
-                p.accel[a] = float(val[a])
+                arr[a] = float(val[a])
         elif key in ("name", "steps", "precision", "check_interval", "lattice"):
             continue
         else:

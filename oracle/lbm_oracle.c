@@ -25,7 +25,13 @@
  *       (g_k = -g*_kbar + 2 omega_k sigma T_w), bounce-back for adiabatic g.
  *       The paper itself used non-equilibrium extrapolation (Sec. 4).
  *       A link leaving through several wall faces takes the first of them in
- *       face order (-x,+x,-y,+y,-z,+z) for its wall velocity.
+ *       face order (-x,+x,-y,+y,-z,+z) for its wall velocity; a wall face
+ *       takes precedence over an outlet face.  Outlets are open boundaries
+ *       at rho0: the incoming population is the anti-bounce-back of the
+ *       outgoing one to twice the even part of f^eq(rho0, u) (Eq. 24 / 18),
+ *       f_ibar = -f*_i + 2 w_i rho0 [1 + (e.u)^2/(2 phi cs^4) - u^2/(2 phi cs^2)],
+ *       with u the node's own velocity at the time of the collision; for g the
+ *       same with the node's own temperature, g_kbar = -g*_k + 2 omega_k sigma T.
  *   R6  Buoyancy G = gbeta (T - T0) along +gravity_axis (hot fluid rises).
  *   R7  Halfway walls: L = n along length_axis, K = Da L^2.
  */
@@ -402,6 +408,7 @@ struct ref_lattice {
   double *f, *g;         /* pre-collision state */
   double *fp, *gp;       /* post-collision */
   double *accel;         /* optional [3][n] */
+  double *mac;           /* [4][n]: u and T of the last collision (outlet rule) */
   int64_t t;
 };
 
@@ -499,9 +506,10 @@ static int check_params(const ref_params* p) {
       return REF_ERR_INVALID_ARG;
     for (int s = 0; s < 2; ++s) {
       const ref_face* fc = &p->face[2 * a + s];
-      if (fc->flow != REF_FLOW_PERIODIC && fc->flow != REF_FLOW_WALL) return REF_ERR_UNSUPPORTED;
+      if (fc->flow != REF_FLOW_PERIODIC && fc->flow != REF_FLOW_WALL && fc->flow != REF_FLOW_OUTLET)
+        return REF_ERR_UNSUPPORTED;
       if (fc->heat != REF_HEAT_PERIODIC && fc->heat != REF_HEAT_ADIABATIC &&
-          fc->heat != REF_HEAT_ISOTHERMAL)
+          fc->heat != REF_HEAT_ISOTHERMAL && fc->heat != REF_HEAT_OUTFLOW)
         return REF_ERR_UNSUPPORTED;
     }
   }
@@ -574,16 +582,17 @@ int ref_create(const ref_params* p, ref_lattice** out) {
   h->fp = (double*)malloc(sizeof(double) * N * q);
   h->g = (double*)malloc(sizeof(double) * N * 7);
   h->gp = (double*)malloc(sizeof(double) * N * 7);
-  if (!h->f || !h->fp || !h->g || !h->gp) {
+  h->mac = (double*)malloc(sizeof(double) * N * 4);
+  if (!h->f || !h->fp || !h->g || !h->gp || !h->mac) {
     ref_destroy(h);
     return REF_ERR_OUT_OF_MEMORY;
   }
 
-  /* initial state: f = f^eq(rho0, 0) (Eq. 24 / Eq. 18), g = g^eq(T, 0) (Eq. 42) */
+  /* initial state: f = f^eq(rho0, u0) (Eq. 24 / Eq. 18), g = g^eq(T, u0) (Eq. 42) */
   const int dims[3] = {p->nx, p->ny, p->nz};
-  const double zero[3] = {0.0, 0.0, 0.0};
+  const double* u0 = p->init_u;
   double feq[19];
-  ref_feq(q, RHO0, zero, p->porosity, feq);
+  ref_feq(q, RHO0, u0, p->porosity, feq);
   for (long long n = 0; n < h->n; ++n) {
     int c[3];
     node_xyz(h, n, &c[0], &c[1], &c[2]);
@@ -595,7 +604,7 @@ int ref_create(const ref_params* p, ref_lattice** out) {
     const double noise = ref_noise(p->seed, (uint64_t)n, p->noise_amp);
     T = T + noise;
     double geq[7];
-    ref_geq(T, zero, p->sigma, p->varpi, geq);
+    ref_geq(T, u0, p->sigma, p->varpi, geq);
     for (int i = 0; i < q; ++i) h->f[(size_t)i * N + n] = feq[i];
     for (int k = 0; k < 7; ++k) h->g[(size_t)k * N + n] = geq[k];
   }
@@ -611,6 +620,7 @@ void ref_destroy(ref_lattice* h) {
   free(h->g);
   free(h->gp);
   free(h->accel);
+  free(h->mac);
   free(h);
 }
 
@@ -711,23 +721,27 @@ int ref_collide_node(const ref_lattice* h, const double* f, const double* g, dou
 
 /* Destination of a link from node (x,y,z) along e: returns 1 and the
  * destination index if the link stays in the box (periodic faces wrap),
- * otherwise 0 and the first wall face crossed in face order (R5). */
+ * otherwise 0 and the face whose rule applies: the first wall face crossed in
+ * face order, else the first outlet face crossed (R5). */
 static int link_target(const ref_lattice* h, const int c[3], const int e[3], long long* dst,
                        int* face) {
   const int dims[3] = {h->p.nx, h->p.ny, h->p.nz};
   int d[3];
-  int hit = -1;
+  int hit = -1, outlet = -1;
   for (int a = 0; a < 3; ++a) {
     d[a] = c[a] + e[a];
     if (d[a] < 0 || d[a] >= dims[a]) {
       const int fc = 2 * a + (d[a] < 0 ? 0 : 1);
       if (h->p.face[fc].flow == REF_FLOW_PERIODIC) {
         d[a] = (d[a] + dims[a]) % dims[a];
+      } else if (h->p.face[fc].flow == REF_FLOW_OUTLET) {
+        if (outlet < 0) outlet = fc;
       } else if (hit < 0) {
         hit = fc;
       }
     }
   }
+  if (hit < 0) hit = outlet;
   if (hit >= 0) {
     *face = hit;
     return 0;
@@ -744,10 +758,12 @@ int ref_step(ref_lattice* h, int64_t nsteps) {
     /* collide every node */
 #pragma omp parallel for schedule(static)
     for (long long n = 0; n < N; ++n) {
-      double f[19], g[7], fo[19], go[7];
+      double f[19], g[7], fo[19], go[7], u[3], T;
       for (int i = 0; i < q; ++i) f[i] = h->f[(size_t)i * N + n];
       for (int k = 0; k < 7; ++k) g[k] = h->g[(size_t)k * N + n];
-      collide(h, n, f, g, fo, go, NULL, NULL, NULL, NULL);
+      collide(h, n, f, g, fo, go, NULL, u, &T, NULL);
+      for (int a = 0; a < 3; ++a) h->mac[(size_t)a * N + n] = u[a];
+      h->mac[(size_t)3 * N + n] = T;
       for (int i = 0; i < q; ++i) h->fp[(size_t)i * N + n] = fo[i];
       for (int k = 0; k < 7; ++k) h->gp[(size_t)k * N + n] = go[k];
     }
@@ -763,6 +779,15 @@ int ref_step(ref_lattice* h, int64_t nsteps) {
         const double v = h->fp[(size_t)i * N + n];
         if (link_target(h, c, e, &dst, &face)) {
           h->f[(size_t)i * N + dst] = v;
+        } else if (h->p.face[face].flow == REF_FLOW_OUTLET) {
+          /* open boundary at rho0 (R5) */
+          const int o = h->opp[i];
+          const double u[3] = {h->mac[n], h->mac[(size_t)N + n], h->mac[(size_t)2 * N + n]};
+          const double eu = h->e[0][o] * u[0] + h->e[1][o] * u[1] + h->e[2][o] * u[2];
+          const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+          const double phi = h->p.porosity;
+          const double even = h->w[o] * RHO0 * (1.0 + eu * eu / (2.0 * phi * CS2 * CS2) - uu / (2.0 * phi * CS2));
+          h->f[(size_t)o * N + n] = -v + 2.0 * even;
         } else {
           /* bounce back into this node along the opposite direction (R5) */
           const int o = h->opp[i];
@@ -782,6 +807,8 @@ int ref_step(ref_lattice* h, int64_t nsteps) {
           const int o = h->opp7[k];
           if (h->p.face[face].heat == REF_HEAT_ISOTHERMAL)
             h->g[(size_t)o * N + n] = -v + 2.0 * h->om[o] * h->p.sigma * h->p.face[face].T_wall;
+          else if (h->p.face[face].heat == REF_HEAT_OUTFLOW)
+            h->g[(size_t)o * N + n] = -v + 2.0 * h->om[o] * h->p.sigma * h->mac[(size_t)3 * N + n];
           else
             h->g[(size_t)o * N + n] = v;
         }

@@ -38,10 +38,13 @@ extern "C" {
 /* flow rule of a face */
 #define REF_FLOW_PERIODIC 0
 #define REF_FLOW_WALL 1      /* halfway bounce-back; u_wall adds the moving-wall term */
+#define REF_FLOW_OUTLET 3    /* open boundary at rho0: anti-bounce-back to the even part
+                                of f^eq(rho0, u) with u the node's own velocity */
 /* thermal rule of a face */
 #define REF_HEAT_PERIODIC 0
 #define REF_HEAT_ADIABATIC 1   /* bounce-back of g: zero normal flux */
 #define REF_HEAT_ISOTHERMAL 2  /* anti-bounce-back of g to T_wall */
+#define REF_HEAT_OUTFLOW 3     /* anti-bounce-back to the node's own temperature */
 
 typedef struct {
   int32_t flow;
@@ -78,6 +81,7 @@ typedef struct {
   double init_T_hi;        /* ... to init_T_hi at the n-1/2 face */
   uint64_t seed;
   double noise_amp;        /* T += noise_amp*(2r-1), r from SplitMix64(seed ^ n) */
+  double init_u[3];        /* initial velocity: f = f^eq(rho0, init_u), g = g^eq(T, init_u) */
 } ref_params;
 
 typedef struct {

@@ -203,14 +203,17 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Deterministic block sum of NV values (max for the entries flagged in is_max);
-// result valid in thread 0.  blockDim.x is a multiple of 64 and <= kMaxBlock.
+// Deterministic block reduction of NV values: a sum, or a max (NaN-propagating)
+// for the entries whose bit is set in maxmask; result valid in thread 0.
+// blockDim.x is a multiple of 64 and <= kMaxBlock.
+__device__ __forceinline__ double pick_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
 template <int NV>
-__device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV]) {
+__device__ __forceinline__ void block_reduce(double (&v)[NV], unsigned maxmask) {
   __shared__ double sh[kMaxBlock / 64][NV];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-  for (int j = 0; j < NV; ++j) v[j] = is_max[j] ? wave_max(v[j]) : wave_sum(v[j]);
+  for (int j = 0; j < NV; ++j) v[j] = ((maxmask >> j) & 1u) ? wave_max(v[j]) : wave_sum(v[j]);
   if (lane == 0) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) sh[wid][j] = v[j];
@@ -220,10 +223,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_ma
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       double a = sh[0][j];
-      for (int w = 1; w < nw; ++w) {
-        const double b = sh[w][j];
-        a = is_max[j] ? ((b > a || b != b) ? b : a) : a + b;
-      }
+      for (int w = 1; w < nw; ++w) a = ((maxmask >> j) & 1u) ? pick_max(a, sh[w][j]) : a + sh[w][j];
       v[j] = a;
     }
   }
@@ -275,8 +275,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const KParams<C> kp, S* __re
     scatter<Lat, ODD, S, C>(kp, state, n, nb, h, p);
   }
   if constexpr (MODE == kModeCompare) {
-    constexpr bool is_max[5] = {false, false, false, false, true};
-    block_reduce<5>(red, is_max);
+    block_reduce<5>(red, 1u << 4);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int j = 0; j < 5; ++j) part[(size_t)blockIdx.x * kPartStride + j] = red[j];
@@ -284,20 +283,35 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const KParams<C> kp, S* __re
   }
 }
 
-// Reduces the per-block partials of a compare step to the residual.
-// res[0] = r, res[1] = unstable (0/1), res[2..6] = the five totals;
-// res[7] (sticky) |= unstable.
-__global__ void __launch_bounds__(kMaxBlock) k_residual_final(const double* __restrict__ part, int nblocks,
+// First stage of the two-stage reduction of per-block partials: block b folds
+// partials [b*blockDim, (b+1)*blockDim) into out[b] (sums; max for maxmask bits).
+__global__ void __launch_bounds__(kMaxBlock) k_fold_partials(const double* __restrict__ in, int count,
+                                                             unsigned maxmask, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i < count) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) v[j] = in[(size_t)i * kPartStride + j];
+  }
+  block_reduce<5>(v, maxmask);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) out[(size_t)blockIdx.x * kPartStride + j] = v[j];
+  }
+}
+
+// Second stage for a compare step: folds the first-stage partials and forms the
+// residual.  res[0] = r, res[1] = unstable (0/1), res[2..6] = the five totals;
+// res[7] (sticky) is set when unstable.
+__global__ void __launch_bounds__(kMaxBlock) k_residual_final(const double* __restrict__ part, int count,
                                                               double* __restrict__ res) {
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+  for (int b = threadIdx.x; b < count; b += blockDim.x) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) v[j] += part[(size_t)b * kPartStride + j];
-    const double m = part[(size_t)b * kPartStride + 4];
-    v[4] = (m > v[4] || m != m) ? m : v[4];
+    v[4] = pick_max(v[4], part[(size_t)b * kPartStride + 4]);
   }
-  constexpr bool is_max[5] = {false, false, false, false, true};
-  block_reduce<5>(v, is_max);
+  block_reduce<5>(v, 1u << 4);
   if (threadIdx.x == 0) {
     auto ratio = [](double num, double den) {
       if (den > 0.0) return sqrt(num / den);
@@ -393,22 +407,22 @@ __global__ void __launch_bounds__(kMaxBlock) k_totals(const KParams<C> kp, const
     for (int i = 0; i < Lat::Q; ++i) v[0] += (double)h[i];
     for (int k = 0; k < 7; ++k) v[1] += (double)p[k];
   }
-  constexpr bool is_max[2] = {false, false};
-  block_reduce<2>(v, is_max);
+  block_reduce<2>(v, 0u);
   if (threadIdx.x == 0) {
     part[(size_t)blockIdx.x * kPartStride + 0] = v[0];
     part[(size_t)blockIdx.x * kPartStride + 1] = v[1];
   }
 }
 
-__global__ void __launch_bounds__(kMaxBlock) k_sum_final(const double* __restrict__ part, int nblocks, int nv,
+// Second stage for the totals: folds the first-stage partials (two sums).
+__global__ void __launch_bounds__(kMaxBlock) k_sum_final(const double* __restrict__ part, int count,
                                                          double* __restrict__ out) {
   double v[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-    for (int j = 0; j < nv && j < 2; ++j) v[j] += part[(size_t)b * kPartStride + j];
+  for (int b = threadIdx.x; b < count; b += blockDim.x) {
+    v[0] += part[(size_t)b * kPartStride + 0];
+    v[1] += part[(size_t)b * kPartStride + 1];
   }
-  constexpr bool is_max[2] = {false, false};
-  block_reduce<2>(v, is_max);
+  block_reduce<2>(v, 0u);
   if (threadIdx.x == 0) {
     out[0] = v[0];
     out[1] = v[1];
@@ -450,8 +464,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, co
       v[0] += 2.0 * pk - shift;
     }
   }
-  constexpr bool is_max[1] = {false};
-  block_reduce<1>(v, is_max);
+  block_reduce<1>(v, 0u);
   if (threadIdx.x == 0) out[face] = v[0];
 }
 

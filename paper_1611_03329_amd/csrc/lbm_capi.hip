@@ -11,7 +11,7 @@
 #include <new>
 #include <string>
 
-#include "../../include/lbm.h"
+#include "lbm.h"
 #include "kernels.hpp"
 
 using namespace lbm;
@@ -56,6 +56,8 @@ struct lbm_lattice {
   void* state = nullptr;
   void* snap = nullptr;
   double* part = nullptr;
+  double* part2 = nullptr;  // first-stage fold of part
+  int nfold = 0;            // entries in part2
   double* res = nullptr;    // [0..7] residual, [8..13] wall flux, [16..17] totals
   int* dev_iso = nullptr;   // [6] isothermal flags
   double* dev_Tw = nullptr; // [6] wall temperatures
@@ -252,8 +254,8 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
 
 // Device layout: [state | snapshot | partials | results | flags].
 struct Layout {
-  size_t state, snap, part, res, iso, Tw, total;
-  int pstride, nblocks, block;
+  size_t state, snap, part, part2, res, iso, Tw, total;
+  int pstride, nblocks, block, nfold;
 };
 
 static Layout layout(const lbm_params* p) {
@@ -271,6 +273,9 @@ static Layout layout(const lbm_params* p) {
   off += align_up((size_t)4 * nodes * s, 256);
   L.part = off;
   off += align_up((size_t)L.nblocks * kPartStride * sizeof(double), 256);
+  L.nfold = (L.nblocks + L.block - 1) / L.block;
+  L.part2 = off;
+  off += align_up((size_t)L.nfold * kPartStride * sizeof(double), 256);
   L.res = off;
   off += 256;
   L.iso = off;
@@ -357,6 +362,8 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   h->state = base + L.state;
   h->snap = base + L.snap;
   h->part = reinterpret_cast<double*>(base + L.part);
+  h->part2 = reinterpret_cast<double*>(base + L.part2);
+  h->nfold = L.nfold;
   h->res = reinterpret_cast<double*>(base + L.res);
   h->dev_iso = reinterpret_cast<int*>(base + L.iso);
   h->dev_Tw = reinterpret_cast<double*>(base + L.Tw);
@@ -470,7 +477,9 @@ extern "C" lbm_status lbm_step(lbm_lattice* h, int64_t nsteps) {
       h->snapshot_at = t;
     }
     if (mode == kModeCompare) {
-      hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, h->stream, h->part, h->nblocks, h->res);
+      hipLaunchKernelGGL(k_fold_partials, dim3(h->nfold), dim3(h->block), 0, h->stream, h->part, h->nblocks,
+                         1u << 4, h->part2);
+      hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, h->stream, h->part2, h->nfold, h->res);
       ls = launch_check("residual");
       if (ls != LBM_OK) return ls;
       HIP_TRY(hipMemcpyAsync(h->host_res, h->res, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -554,7 +563,9 @@ extern "C" lbm_status lbm_totals(lbm_lattice* h, double* mass, double* heat) {
   });
   lbm_status ls = launch_check("totals");
   if (ls != LBM_OK) return ls;
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, h->stream, h->part, h->nblocks, 2, h->res + 16);
+  hipLaunchKernelGGL(k_fold_partials, dim3(h->nfold), dim3(h->block), 0, h->stream, h->part, h->nblocks, 0u,
+                     h->part2);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, h->stream, h->part2, h->nfold, h->res + 16);
   ls = launch_check("totals final");
   if (ls != LBM_OK) return ls;
   HIP_TRY(hipMemcpyAsync(h->host_res + 16, h->res + 16, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));

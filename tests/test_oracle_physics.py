@@ -236,3 +236,35 @@ def test_mixed_convection_channel_eqs_48_49():
     assert eu < 2e-2, eu
     assert eT < 2e-2, eT
     assert np.max(np.abs(uy - u1)) < 0.05 * u1
+
+
+# --------------------------------------------------------------- open boundaries
+@pytest.mark.parametrize("q,forch", [(19, 0.0), (19, 1.0), (15, 1.0)])
+def test_plug_flow_through_porous_slab_obeys_darcy_forchheimer(q, forch):
+    """Uniform inflow U through a moving-wall inlet, an open outlet at rho0:
+    mass conservation makes u = U exactly, and the momentum balance of Eq. 2
+    with Eq. 4 gives cs^2 d(rho)/dx = F = -(phi nu/K) U - (phi F_phi/sqrt K) U^2.
+    The inlet temperature is carried through unchanged."""
+    U, n, phi = 0.02, 48, 0.7
+    per = face("periodic", "periodic")
+    wl = {"nx": n, "ny": 1, "nz": 1, "q": q, "porosity": phi, "darcy": 1e-1, "rayleigh": 0.0,
+          "prandtl": 1.0, "forchheimer": forch, "s_nu_set": 1.2, "zeta_alpha_set": 1.0,
+          "length_axis": 0, "gravity_axis": 1, "T_ref": 0.0, "delta_T": 1.0,
+          "faces": [face("wall", "isothermal", 0.3, (U, 0.0, 0.0)), face("outlet", "outflow"),
+                    per, per, per, per],
+          "init_axis": -1, "noise_amp": 0.0, "init_u": (U, 0.0, 0.0)}
+    with oracle.Oracle(wl) as o:
+        d = o.derived()
+        _run_to_steady(o, "rho", chunk=2000, tol=1e-13)
+        fl = o.fields()
+    ux, rho, T = fl["ux"][0, 0], fl["rho"][0, 0], fl["T"][0, 0]
+    F = -phi * d["nu"] / d["K"] * U - phi * d["F_phi"] / np.sqrt(d["K"]) * U * U
+    slope = np.polyfit(np.arange(n), rho, 1)[0]
+    assert np.max(np.abs(ux - U)) < 1e-13
+    # (exact to 1e-12 for D3Q19; D3Q15 carries an O(U^2 drho) compressibility term)
+    assert abs(slope / (F / (1.0 / 3.0)) - 1.0) < 1e-6
+    # linear away from the last nodes (D3Q15 has a thin outlet layer in rho)
+    assert np.max(np.abs(np.diff(rho)[:-4] - slope)) < 1e-5 * abs(slope)
+    # the open boundary holds rho0 at the outlet face to O(U^2)
+    assert abs(rho[-1] + 0.5 * slope - 1.0) < U * U
+    assert np.max(np.abs(T - 0.3)) < 1e-13
