@@ -75,6 +75,9 @@ def main(argv=None) -> int:
     ap.add_argument("--check-interval", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps on the 256^3 sample (0 skips the CPU baseline)")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30,
+                    help="size of the plain device-to-device copy timed as the attainable-bandwidth "
+                         "reference (0 skips it)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -91,6 +94,24 @@ def main(argv=None) -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    copy_gbps = None
+    if args.copy_bytes > 0:
+        # plain copy of a known size: the reference the HBM byte counters are scaled by
+        a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(10):
+            b.copy_(a)
+        c1.record()
+        torch.cuda.synchronize()
+        copy_gbps = 2 * args.copy_bytes * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
+        del a, b
+        torch.cuda.empty_cache()
     wl = lbm_inputs.config_cavity_fp32()
     lat = Lattice(wl, "fp32", check_interval=args.check_interval)
     nodes = lat.nodes
@@ -117,7 +138,8 @@ def main(argv=None) -> int:
     achieved = bytes_per_node * nodes / (ms_per_step / 1e3) / 1e9
     traffic = traffic_from_profiles(nodes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic}
+                "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
+                "copy_reference_GBps": None if copy_gbps is None else round(copy_gbps, 1)}
 
     cpu = None
     if args.cpu_steps > 0:

@@ -52,6 +52,7 @@ extern "C" {
 #endif
 
 typedef struct lbm_lattice lbm_lattice; /* opaque */
+typedef struct lbm_batch lbm_batch;     /* opaque */
 
 typedef enum {
   LBM_OK = 0,
@@ -63,12 +64,26 @@ typedef enum {
 } lbm_status;
 
 typedef enum {
-  LBM_FP64 = 0, /* populations stored and computed in FP64 */
-  LBM_FP32 = 1  /* populations stored and computed in FP32 (stored shifted by rest weights) */
-} lbm_precision;
+  LBM_FP64 = 0,        /* populations stored and computed in FP64 */
+  LBM_FP32 = 1,        /* populations stored and computed in FP32 */
+  LBM_FP16_STORAGE = 2 /* moving flow populations stored in FP16; temperature and rest
+                          populations in FP32; arithmetic in FP32 */
+} lbm_precision;       /* in every mode populations are stored shifted by their rest state */
 
-typedef enum { LBM_FLOW_PERIODIC = 0, LBM_FLOW_WALL = 1 } lbm_flow_bc;
-typedef enum { LBM_HEAT_PERIODIC = 0, LBM_HEAT_ADIABATIC = 1, LBM_HEAT_ISOTHERMAL = 2 } lbm_heat_bc;
+/* Face rules.  WALL: halfway bounce-back (u_wall: moving wall; a wall velocity
+ * with a normal component makes the face an inlet).  OUTLET: open boundary at
+ * rho0: the entering population is the anti-bounce-back of the leaving one to
+ * twice the even part of f^eq(rho0, u), u the node's own velocity when it
+ * collided.  For g, OUTFLOW is the anti-bounce-back to the node's own
+ * temperature.  A link that leaves through a wall face and an open face takes
+ * the wall rule. */
+typedef enum { LBM_FLOW_PERIODIC = 0, LBM_FLOW_WALL = 1, LBM_FLOW_OUTLET = 3 } lbm_flow_bc;
+typedef enum {
+  LBM_HEAT_PERIODIC = 0,
+  LBM_HEAT_ADIABATIC = 1,
+  LBM_HEAT_ISOTHERMAL = 2,
+  LBM_HEAT_OUTFLOW = 3
+} lbm_heat_bc;
 
 /* One face of the box.  Face order: 0 = -x, 1 = +x, 2 = -y, 3 = +y, 4 = -z, 5 = +z.
  * Opposite faces are both periodic (flow and heat) or both not. */
@@ -111,6 +126,7 @@ typedef struct {
   uint64_t seed;          /* ... plus noise_amp*(2r-1), r = (SplitMix64(seed ^ n) >> 11) * 2^-53 */
   double noise_amp;
   int32_t check_interval; /* K > 0: residual check at every multiple of K steps; 0 disables */
+  double init_u[3];       /* initial velocity: f = f^eq(rho0, init_u), g = g^eq(T, init_u) */
 } lbm_params;
 
 /* Derived quantities (Eqs. 6, 7, 28, 32, 41, 51, 56). */
@@ -127,8 +143,8 @@ void lbm_default_params(lbm_params* p);
  * parameters lbm_create would reject; *bytes is 0 then. */
 lbm_status lbm_required_bytes(const lbm_params* p, size_t* bytes);
 
-/* Creates a lattice and enqueues its initialisation (f = f^eq(rho0, 0) of Eq. 24/18,
- * g = g^eq(T_init, 0) of Eq. 42) on `stream` (a hipStream_t; NULL = null stream).
+/* Creates a lattice and enqueues its initialisation (f = f^eq(rho0, init_u) of
+ * Eq. 24/18, g = g^eq(T_init, init_u) of Eq. 42) on `stream` (a hipStream_t; NULL = null stream).
  * dev_buf: caller-owned device memory of at least lbm_required_bytes() bytes,
  * 256-byte aligned, kept alive until lbm_destroy; or NULL, in which case the
  * library allocates (and later frees) it.  Parameters are validated before any
@@ -189,6 +205,81 @@ lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g);
  * lbm_get_state; both required), rounding to the storage precision.  The time
  * counter is kept; the pending residual snapshot is discarded.  Asynchronous. */
 lbm_status lbm_set_state(lbm_lattice* h, const double* f, const double* g);
+
+/* ---------------------------------------------------------------- batches
+ * A batch advances many independent lattices (members) by the same fused time
+ * step of lbm_step, with one kernel launch per step for all members (two when
+ * some members have moving walls or open faces and others not).  A member's
+ * state after any number of steps is bit for bit the one lbm_step gives it,
+ * and its residuals depend on nothing else in the batch (they are summed in a
+ * fixed order set by the member's size and the block size alone).
+ * Members share lattice type, precision and stream (the batch's), and the time
+ * parity; lbm_batch_add takes one lbm_step of the joining lattice when its
+ * parity differs.  The residual check (lbm_residual) follows the batch's own
+ * step counter s: with check interval K > 0 the steps s = mK-1 and s = mK of
+ * the batch compute every member's r at its own time; a member's first check
+ * comes at the first such pair after it joined.  While in a batch a lattice
+ * may be queried (lbm_fields, lbm_nusselt, lbm_residual, lbm_totals,
+ * lbm_get_state) but not stepped, given a state or a stream of its own; the
+ * queries enqueue on the batch's stream.  lbm_destroy of a member removes it
+ * first.  A batch is not thread-safe. */
+
+/* Creates an empty batch that enqueues on `stream` (hipStream_t; NULL = null
+ * stream) and checks residuals every check_interval >= 0 batch steps.
+ * Allocates no device memory yet. */
+lbm_status lbm_batch_create(void* stream, int32_t check_interval, lbm_batch** out);
+
+/* Waits for the batch's stream, leaves every member a plain lattice (its last
+ * batch residual kept) and frees the batch.  NULL is accepted. */
+lbm_status lbm_batch_destroy(lbm_batch* b);
+
+/* Adds lattice h (not in a batch).  Returns LBM_ERR_UNSUPPORTED if its lattice
+ * type or precision differs from the members'.  Synchronizes h's old stream if
+ * it differs from the batch's.  May enqueue one step of h. */
+lbm_status lbm_batch_add(lbm_batch* b, lbm_lattice* h);
+
+/* Removes member h (a plain lattice again, on the batch's stream, with its
+ * time and its last batch residual).  Synchronizes. */
+lbm_status lbm_batch_remove(lbm_batch* b, lbm_lattice* h);
+
+/* Number of members; member `index` in join order (removals close the gap). */
+lbm_status lbm_batch_size(const lbm_batch* b, int32_t* count);
+lbm_status lbm_batch_member(const lbm_batch* b, int32_t index, lbm_lattice** out);
+
+/* Enqueues nsteps >= 0 steps of every member.  An unstable member keeps being
+ * stepped (its values are then meaningless) until the caller removes it; the
+ * others are unaffected.  Asynchronous, except that the first step after a
+ * change of membership or launch shape, or after a member's first snapshot,
+ * synchronizes once to upload the member table. */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
+
+/* Per member, in join order, into host arrays of `count` (= the member count)
+ * entries, any of them NULL to skip: the most recent residual r (-1 if none),
+ * the member time it was taken at (-1), and 1 if that check found the member
+ * unstable.  Synchronizes. */
+lbm_status lbm_batch_residuals(lbm_batch* b, double* r, int64_t* at_step, int32_t* unstable, int32_t count);
+
+/* Launch shape of the batch kernel: `block` threads per tile (64, 128 or 256;
+ * default 256) and, if blocks_per_cu > 0, a persistent grid of blocks_per_cu
+ * blocks per compute unit (at most the tile count) whose blocks walk the tile
+ * list; 0 (default) launches one block per tile.  Results do not depend on the
+ * launch shape except through the residual's summation order, which follows
+ * `block`. */
+lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu);
+
+/* Runs 1 + steps batch steps at each launch shape (block in {64, 128, 256} x
+ * blocks_per_cu in {0, 4, 8, 16}), times the last `steps` with HIP events (graph
+ * replay off meanwhile) and keeps the fastest; writes it to *block and
+ * *blocks_per_cu where non-NULL.  The steps advance the members.
+ * Synchronizes. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* block, int32_t* blocks_per_cu);
+
+/* on != 0: whole check intervals (the K steps from a batch step s with
+ * s % K == 0) are recorded once into a HIP graph and replayed; the graph is
+ * recorded again when the member table outgrows its buffers or the member
+ * count or launch shape changes.  Needs K > 0 and a created stream
+ * (capture is impossible on the null stream): LBM_ERR_UNSUPPORTED otherwise. */
+lbm_status lbm_batch_set_graph(lbm_batch* b, int32_t on);
 
 const char* lbm_status_string(lbm_status s);
 const char* lbm_last_error(void);

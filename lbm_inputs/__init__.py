@@ -86,3 +86,70 @@ def random_state(q: int, shape, seed: int, *, f_base=None, amp=0.05, T_amp=0.5):
     g = np.broadcast_to(T / 7.0, (7, nz, ny, nx)) * (1.0 + amp * rng.uniform(
         -1.0, 1.0, size=(7, nz, ny, nx)))
     return np.ascontiguousarray(f), np.ascontiguousarray(g)
+
+
+def channel(shape, *, lattice=15, porosity=0.7, darcy=1e-3, reynolds=10.0, rayleigh=1e5,
+            prandtl=1.0, u_in=0.05, seed=3, noise_amp=1e-3, T_hot=0.5, T_cold=-0.5,
+            forchheimer=1.0, **extra) -> dict:
+    """Mixed convection in a porous channel (the setting of Sec. 4.1, here with a
+    throughflow): plug inflow u_in through the -x face (moving-wall bounce-back,
+    inlet temperature T_ref), open outlet at +x, heated bottom wall (-y, T_hot)
+    and cooled top wall (+y, T_cold), periodic in z, buoyancy along +y.
+    Re = u_in H / nu with H = ny.  Initial state: plug flow, T linear in y plus
+    seeded uniform noise."""
+    nx, ny, nz = shape
+    T_ref = 0.5 * (T_hot + T_cold)
+    wl = {
+        "nx": int(nx), "ny": int(ny), "nz": int(nz), "q": int(lattice),
+        "porosity": float(porosity), "darcy": float(darcy), "rayleigh": float(rayleigh),
+        "prandtl": float(prandtl), "reynolds": float(reynolds), "u_char": float(u_in),
+        "forchheimer": float(forchheimer), "gravity_axis": 1, "length_axis": 1,
+        "T_ref": T_ref, "delta_T": float(T_hot - T_cold),
+        "faces": [face("wall", "isothermal", T_ref, (u_in, 0.0, 0.0)), face("outlet", "outflow"),
+                  face("wall", "isothermal", T_hot), face("wall", "isothermal", T_cold),
+                  face("periodic", "periodic"), face("periodic", "periodic")],
+        "init_axis": 1, "init_T_lo": float(T_hot), "init_T_hi": float(T_cold),
+        "seed": int(seed), "noise_amp": float(noise_amp), "init_u": (float(u_in), 0.0, 0.0),
+    }
+    wl.update(extra)
+    return wl
+
+
+def config_channel(downscale: bool = False) -> dict:
+    """Porous channel 512x128x128 (or its 128x32x32 downscale), D3Q15 + D3Q7:
+    phi 0.7, Da 1e-3, Re 10, Ra 1e5, inlet 0.05, seed 3."""
+    shape = (128, 32, 32) if downscale else (512, 128, 128)
+    wl = channel(shape)
+    wl.update(name="channel%dx%dx%d" % shape)
+    return wl
+
+
+def _cavity_draw(rng, edge: int, index: int, seed: int) -> dict:
+    """One cavity of the batched and served workloads: porosity U[0.3, 0.9],
+    Da log-uniform in [1e-5, 1e-1], Ra log-uniform in [1e3, 1e6], Pr 1."""
+    phi = float(rng.uniform(0.3, 0.9))
+    da = float(10.0 ** rng.uniform(-5.0, -1.0))
+    ra = float(10.0 ** rng.uniform(3.0, 6.0))
+    wl = cavity(int(edge), porosity=phi, darcy=da, rayleigh=ra, prandtl=1.0, seed=seed * 1000 + index)
+    wl["name"] = f"cavity{edge}_phi{phi:.3f}_Da{da:.2e}_Ra{ra:.2e}"
+    return wl
+
+
+def config_batch(count: int = 64, seed: int = 4) -> list:
+    """Independent porous cubic cavities with edge length drawn uniformly from
+    {32, 48, 64, 96, 128} and parameters drawn as in ``_cavity_draw``."""
+    rng = np.random.default_rng(seed)
+    edges = rng.choice(np.array([32, 48, 64, 96, 128]), size=count)
+    return [_cavity_draw(rng, int(e), i, seed) for i, e in enumerate(edges)]
+
+
+def config_serving(count: int = 64, rate: float = 20.0, seed: int = 5, edge_range=(48, 192)) -> list:
+    """A Poisson stream of cavity solve requests: exponential inter-arrival
+    times of mean 1/rate seconds, edge length log-uniform in edge_range
+    (rounded to an integer), parameters as in ``_cavity_draw``.  Returns
+    (arrival_seconds, workload) pairs in arrival order."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    lo, hi = np.log(edge_range[0]), np.log(edge_range[1])
+    edges = np.rint(np.exp(rng.uniform(lo, hi, size=count))).astype(int)
+    return [(float(t[i]), _cavity_draw(rng, int(edges[i]), i, seed)) for i in range(count)]

@@ -29,16 +29,75 @@ namespace lbm {
 constexpr int kMaxBlock = 256;
 
 // ------------------------------------------------------------------ storage
-template <class S, class C>
-__device__ __forceinline__ C ld(const S* p) {
-  return static_cast<C>(*p);
+// Element e of the state, addressed as base + 32-bit byte offset (the host
+// keeps every lattice's state below 4 GiB), which maps onto the scalar-base +
+// vector-offset form of the global memory instructions.
+// The state always lives in device global memory; saying so keeps the compiler
+// on global (not flat) instructions also where the base pointer was itself
+// loaded from memory (the batch kernel's member table).
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ LBM_GLOBAL T* gbl(T* p) {
+  return (LBM_GLOBAL T*)p;
 }
 template <class S, class C>
-__device__ __forceinline__ void st(S* p, C v) {
-  *p = static_cast<S>(v);
+__device__ __forceinline__ C ld(const S* base, uint32_t e) {
+  const LBM_GLOBAL char* b = (const LBM_GLOBAL char*)base;
+  return static_cast<C>(*(const LBM_GLOBAL S*)(b + e * (uint32_t)sizeof(S)));
+}
+template <class S, class C>
+__device__ __forceinline__ void st(S* base, uint32_t e, C v) {
+  LBM_GLOBAL char* b = (LBM_GLOBAL char*)base;
+  *(LBM_GLOBAL S*)(b + e * (uint32_t)sizeof(S)) = static_cast<S>(v);
 }
 
+// Population storage in three regions: the moving flow populations f_1..f_{Q-1}
+// (type Mf), the moving temperature populations g_1..g_6 (type Mg) and the two
+// rest populations f_0, g_0 (type Rs), which never leave their node.  With FP16
+// storage only the moving flow populations are FP16: the heat flux is carried
+// by the difference of opposite g populations, far below FP16's resolution of
+// each of them, and the rest populations change only through the collision, by
+// amounts FP16 would round away.
+template <class Mf, class Mg, class Rs>
+struct Store {
+  using MoveF = Mf;
+  using MoveG = Mg;
+  using Rest = Rs;
+  Mf* mf;
+  Mg* mg;
+  Rs* rs;
+};
+
+// plane of moving flow population i >= 1 and temperature population k >= 1
+template <class Lat>
+__host__ __device__ constexpr uint32_t fplane(int i) { return (uint32_t)(i - 1); }
+template <class Lat>
+__host__ __device__ constexpr uint32_t gplane(int k) { return (uint32_t)(k - 1); }
+
+template <class S, class C>
+__device__ __forceinline__ C ld_mf(const S& s, uint32_t e) { return ld<typename S::MoveF, C>(s.mf, e); }
+template <class S, class C>
+__device__ __forceinline__ C ld_mg(const S& s, uint32_t e) { return ld<typename S::MoveG, C>(s.mg, e); }
+template <class S, class C>
+__device__ __forceinline__ C ld_rs(const S& s, uint32_t e) { return ld<typename S::Rest, C>(s.rs, e); }
+template <class S, class C>
+__device__ __forceinline__ void st_mf(const S& s, uint32_t e, C v) { st<typename S::MoveF, C>(s.mf, e, v); }
+template <class S, class C>
+__device__ __forceinline__ void st_mg(const S& s, uint32_t e, C v) { st<typename S::MoveG, C>(s.mg, e, v); }
+template <class S, class C>
+__device__ __forceinline__ void st_rs(const S& s, uint32_t e, C v) { st<typename S::Rest, C>(s.rs, e, v); }
+
 // ------------------------------------------------------------------ geometry
+// Coordinates of node n: exact division by an FP64 reciprocal rounded up
+// (kp.inv_nx, kp.inv_nxy), valid for n < 2^31.
+template <class C>
+__device__ __forceinline__ void node_coords(const KParams<C>& kp, int n, int& x, int& y, int& z) {
+  const int yz = (int)((double)n * kp.inv_nx);
+  z = (int)((double)n * kp.inv_nxy);
+  x = n - yz * kp.nx;
+  y = yz - z * kp.ny;
+}
+
 // Offsets (in nodes) to the neighbour at coordinate -1 / +1 along each axis,
 // with periodic wrap, and whether that neighbour exists.
 struct Nbr {
@@ -63,32 +122,66 @@ __device__ __forceinline__ Nbr make_nbr(const KParams<C>& kp, int x, int y, int 
   return b;
 }
 
-// Link along velocity (ex, ey, ez) taken with sign `sg` (+1: to x + e, -1: to x - e).
-struct Link {
-  int off;
-  bool in;
-  int face;  // first wall face crossed (face order), valid when !in
-};
-
+// Link along velocity e taken with sign SG (+1: to x + e, -1: to x - e):
+// node offset and whether the linked node exists.
 template <int EX, int EY, int EZ, int SG>
-__device__ __forceinline__ Link link(const Nbr& b) {
-  Link L{0, true, 0};
-  int face = -1;
-  auto axis = [&](auto A, int e) {
-    constexpr int a = decltype(A)::value;
+__device__ __forceinline__ void link(const Nbr& b, int& off, bool& in) {
+  off = 0;
+  in = true;
+  if constexpr (EX != 0) {
+    constexpr int s = EX * SG > 0 ? 1 : 0;
+    off += b.off[0][s];
+    in = in && b.in[0][s];
+  }
+  if constexpr (EY != 0) {
+    constexpr int s = EY * SG > 0 ? 1 : 0;
+    off += b.off[1][s];
+    in = in && b.in[1][s];
+  }
+  if constexpr (EZ != 0) {
+    constexpr int s = EZ * SG > 0 ? 1 : 0;
+    off += b.off[2][s];
+    in = in && b.in[2][s];
+  }
+}
+
+// For a link that leaves the box: the face whose rule applies (the first wall
+// face crossed in face order, else the first open face crossed) and whether it
+// is an open face.  Open faces are those in open_mask.
+template <int EX, int EY, int EZ, int SG>
+__device__ __forceinline__ int exit_face(const Nbr& b, int open_mask, bool& open) {
+  int wall = -1, opn = -1;
+  auto axis = [&](int a, int e) {
     if (e == 0) return;
-    const int side = (e * SG > 0) ? 1 : 0;
-    L.off += b.off[a][side];
+    const int side = e * SG > 0 ? 1 : 0;
     if (!b.in[a][side]) {
-      L.in = false;
-      if (face < 0) face = 2 * a + side;
+      const int fc = 2 * a + side;
+      if ((open_mask >> fc) & 1) {
+        opn = opn < 0 ? fc : opn;
+      } else {
+        wall = wall < 0 ? fc : wall;
+      }
     }
   };
-  axis(std::integral_constant<int, 0>{}, EX);
-  axis(std::integral_constant<int, 1>{}, EY);
-  axis(std::integral_constant<int, 2>{}, EZ);
-  L.face = face < 0 ? 0 : face;
-  return L;
+  axis(0, EX);
+  axis(1, EY);
+  axis(2, EZ);
+  open = wall < 0 && opn >= 0;
+  return wall >= 0 ? wall : (opn >= 0 ? opn : 0);
+}
+
+// Face crossed by a D3Q7 link (one axis), known at compile time.
+template <int K, int SG>
+constexpr int d3q7_face() {
+  constexpr int a = D3Q7::e(0, K) != 0 ? 0 : (D3Q7::e(1, K) != 0 ? 1 : 2);
+  constexpr int e = D3Q7::e(a, K);
+  return 2 * a + (e * SG > 0 ? 1 : 0);
+}
+
+template <class Lat, int J>
+__host__ __device__ constexpr double weight() {
+  if constexpr (Lat::Q == 19) return Lat::w36(J) / 36.0;
+  else return Lat::w72(J) / 72.0;
 }
 
 // Moving-wall term of bounce-back for the population entering along direction j:
@@ -104,46 +197,77 @@ __device__ __forceinline__ C wall_term(const KParams<C>& kp, int face) {
     for (int f = 1; f < 6; ++f) v = face == f ? kp.u_wall[f][a] : v;
     uw[a] = v;
   }
-  C w6;
-  if constexpr (Lat::Q == 19) w6 = C(6.0 * Lat::w36(J) / 36.0);
-  else w6 = C(6.0 * Lat::w72(J) / 72.0);
-  return w6 * (C(ex) * uw[0] + C(ey) * uw[1] + C(ez) * uw[2]);
+  return C(6.0 * weight<Lat, J>()) * (C(ex) * uw[0] + C(ey) * uw[1] + C(ez) * uw[2]);
+}
+
+// Open outlet at rho0: the population entering along direction j is the
+// anti-bounce-back of the outgoing post-collision one to twice the even part of
+// f^eq(rho0, u) (Eq. 24 / 18) at the node's own velocity; shifted:
+// h_j = -h*_jbar + 2 w_j [(e_j.u)^2 / (2 phi cs^4) - u^2 / (2 phi cs^2)].
+template <class Lat, int J, class C>
+__device__ __forceinline__ C open_flow_value(C h_out, const Macro<C>& M, C inv_phi) {
+  constexpr int ex = Lat::e(0, J), ey = Lat::e(1, J), ez = Lat::e(2, J);
+  const C eu = C(ex) * M.ux + C(ey) * M.uy + C(ez) * M.uz;
+  const C uu = M.ux * M.ux + M.uy * M.uy + M.uz * M.uz;
+  return -h_out + C(2.0 * weight<Lat, J>()) * (C(4.5) * eu * eu - C(1.5) * uu) * inv_phi;
+}
+
+// Outflow face for g: anti-bounce-back to the node's own temperature;
+// shifted: p_k = -p*_kbar + 2 omega_k sigma (T - T_ref), omega_k = varpi / 6.
+template <class C>
+__device__ __forceinline__ C open_heat_value(const KParams<C>& kp, C p_out, const Macro<C>& M) {
+  return -p_out + C(2.0 / 6.0) * kp.varpi * M.dsT;
 }
 
 // ------------------------------------------------------------------ gather
-// Pre-collision shifted populations of node n at the current parity.
-template <class Lat, bool ODD, class S, class C>
-__device__ __forceinline__ void gather(const KParams<C>& kp, const S* __restrict__ st_, int n,
-                                       const Nbr& nb, C (&h)[Lat::Q], C (&p)[7]) {
-  const S* f = st_;
-  const S* g = st_ + (size_t)Lat::Q * kp.pstride;
-  static_for<0, Lat::Q>([&](auto I) {
+// Pre-collision shifted populations of node n at the current parity.  At odd
+// parity a population entering from outside is read from this node's own slot:
+// raw for walls (then the wall rule is applied), already final for open faces
+// (the step that stored it applied the open rule).  GEN = false compiles only
+// the rules of periodic faces and static walls; GEN = true adds moving walls
+// and open faces.
+template <class Lat, bool ODD, bool GEN, class S, class C>
+__device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
+                                       C (&h)[Lat::Q], C (&p)[7]) {
+  const uint32_t ps = (uint32_t)kp.pstride;
+  h[0] = ld_rs<S, C>(sto, (uint32_t)n);
+  static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     if constexpr (!ODD) {
-      h[i] = ld<S, C>(f + (size_t)i * kp.pstride + n);
+      h[i] = ld_mf<S, C>(sto, fplane<Lat>(i) * ps + (uint32_t)n);
     } else {
       constexpr int io = Lat::opp(i);
-      const Link L = link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb);
-      const S* src = L.in ? (f + (size_t)io * kp.pstride + (n + L.off)) : (f + (size_t)i * kp.pstride + n);
-      C v = ld<S, C>(src);
-      if constexpr (i != 0) {
-        if (kp.moving && !L.in) v += wall_term<Lat, i>(kp, L.face);
+      int off;
+      bool in;
+      link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, off, in);
+      const uint32_t e = in ? fplane<Lat>(io) * ps + (uint32_t)(n + off) : fplane<Lat>(i) * ps + (uint32_t)n;
+      C v = ld_mf<S, C>(sto, e);
+      if constexpr (GEN) {
+        if (kp.moving) {
+          bool open;
+          const int fc = exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, kp.open_flow, open);
+          const C t = wall_term<Lat, i>(kp, fc);
+          v = (in || open) ? v : v + t;
+        }
       }
       h[i] = v;
     }
   });
-  static_for<0, 7>([&](auto K) {
+  p[0] = ld_rs<S, C>(sto, ps + (uint32_t)n);
+  static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if constexpr (!ODD) {
-      p[k] = ld<S, C>(g + (size_t)k * kp.pstride + n);
+      p[k] = ld_mg<S, C>(sto, gplane<Lat>(k) * ps + (uint32_t)n);
     } else {
       constexpr int ko = D3Q7::opp(k);
-      const Link L = link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), -1>(nb);
-      const S* src = L.in ? (g + (size_t)ko * kp.pstride + (n + L.off)) : (g + (size_t)k * kp.pstride + n);
-      C v = ld<S, C>(src);
-      if constexpr (k != 0) {
-        if (!L.in) v = kp.heat_a[L.face] * v + kp.heat_b[L.face];
-      }
+      int off;
+      bool in;
+      link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), -1>(nb, off, in);
+      const uint32_t e = in ? gplane<Lat>(ko) * ps + (uint32_t)(n + off) : gplane<Lat>(k) * ps + (uint32_t)n;
+      C v = ld_mg<S, C>(sto, e);
+      // outflow faces carry heat_a = 1, heat_b = 0: their value is already final
+      constexpr int fc = d3q7_face<k, -1>();
+      v = in ? v : kp.heat_a[fc] * v + kp.heat_b[fc];
       p[k] = v;
     }
   });
@@ -151,39 +275,78 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S* __restrict
 
 // ------------------------------------------------------------------ scatter
 // Post-collision shifted populations of node n, written for the next parity.
-template <class Lat, bool ODD, class S, class C>
-__device__ __forceinline__ void scatter(const KParams<C>& kp, S* __restrict__ st_, int n, const Nbr& nb,
-                                        const C (&h)[Lat::Q], const C (&p)[7]) {
-  S* f = st_;
-  S* g = st_ + (size_t)Lat::Q * kp.pstride;
-  static_for<0, Lat::Q>([&](auto I) {
+// M holds the node's macroscopic state (used by the open-face rules).
+template <class Lat, bool ODD, bool GEN, class S, class C>
+__device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
+                                        const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M) {
+  const uint32_t ps = (uint32_t)kp.pstride;
+  st_rs<S, C>(sto, (uint32_t)n, h[0]);
+  static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int io = Lat::opp(i);
     if constexpr (!ODD) {
-      st<S, C>(f + (size_t)io * kp.pstride + n, h[i]);
-    } else {
-      const Link L = link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb);
       C v = h[i];
-      if constexpr (i != 0) {
-        if (kp.moving && !L.in) v += wall_term<Lat, io>(kp, L.face);
+      if constexpr (GEN) {
+        // slot ibar of this node is read back only by this node when i leaves
+        // through an open face: store the open-face value there
+        if (kp.open_flow) {
+          int off;
+          bool in, open;
+          link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, off, in);
+          (void)exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, kp.open_flow, open);
+          const C ov = open_flow_value<Lat, io, C>(v, M, kp.inv_phi);
+          v = (!in && open) ? ov : v;
+        }
       }
-      S* dst = L.in ? (f + (size_t)i * kp.pstride + (n + L.off)) : (f + (size_t)io * kp.pstride + n);
-      st<S, C>(dst, v);
+      st_mf<S, C>(sto, fplane<Lat>(io) * ps + (uint32_t)n, v);
+    } else {
+      int off;
+      bool in;
+      link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, off, in);
+      C v = h[i];
+      if constexpr (GEN) {
+        bool open;
+        const int fc = exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, kp.open_flow, open);
+        const C ov = open_flow_value<Lat, io, C>(v, M, kp.inv_phi);
+        const C wv = kp.moving ? v + wall_term<Lat, io>(kp, fc) : v;
+        v = in ? v : (open ? ov : wv);
+      }
+      const uint32_t e = in ? fplane<Lat>(i) * ps + (uint32_t)(n + off) : fplane<Lat>(io) * ps + (uint32_t)n;
+      st_mf<S, C>(sto, e, v);
     }
   });
-  static_for<0, 7>([&](auto K) {
+  st_rs<S, C>(sto, ps + (uint32_t)n, p[0]);
+  static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int ko = D3Q7::opp(k);
     if constexpr (!ODD) {
-      st<S, C>(g + (size_t)ko * kp.pstride + n, p[k]);
-    } else {
-      const Link L = link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), +1>(nb);
       C v = p[k];
-      if constexpr (k != 0) {
-        if (!L.in) v = kp.heat_a[L.face] * v + kp.heat_b[L.face];
+      if constexpr (GEN) {
+        if (kp.open_heat) {
+          int off;
+          bool in;
+          link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), +1>(nb, off, in);
+          constexpr int fc = d3q7_face<k, +1>();
+          const bool open = (kp.open_heat >> fc) & 1;
+          const C ov = open_heat_value<C>(kp, v, M);
+          v = (!in && open) ? ov : v;
+        }
       }
-      S* dst = L.in ? (g + (size_t)k * kp.pstride + (n + L.off)) : (g + (size_t)ko * kp.pstride + n);
-      st<S, C>(dst, v);
+      st_mg<S, C>(sto, gplane<Lat>(ko) * ps + (uint32_t)n, v);
+    } else {
+      int off;
+      bool in;
+      link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), +1>(nb, off, in);
+      C v = p[k];
+      constexpr int fc = d3q7_face<k, +1>();
+      C bv = kp.heat_a[fc] * v + kp.heat_b[fc];
+      if constexpr (GEN) {
+        const bool open = (kp.open_heat >> fc) & 1;
+        bv = open ? open_heat_value<C>(kp, v, M) : bv;
+      }
+      v = in ? v : bv;
+      const uint32_t e = in ? gplane<Lat>(k) * ps + (uint32_t)(n + off) : gplane<Lat>(ko) * ps + (uint32_t)n;
+      st_mg<S, C>(sto, e, v);
     }
   });
 }
@@ -233,35 +396,33 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], unsigned maxmask) 
 enum : int { kModePlain = 0, kModeSnapshot = 1, kModeCompare = 2 };
 constexpr int kPartStride = 8;  // doubles per block in the partials buffer
 
-// One fused time step for every node.
+// One fused time step of the nodes of one block (block index lb of the lattice).
 //   MODE 1 also stores u and T of the pre-collision state into snap (4 planes of n);
 //   MODE 2 also accumulates, per block, sum|u - u_snap|^2, sum|u|^2,
-//   sum (theta - theta_snap)^2, sum theta^2 and max|u| into part.
-template <class Lat, class S, class C, bool ODD, int MODE>
-__global__ void __launch_bounds__(kMaxBlock) k_step(const KParams<C> kp, S* __restrict__ state,
-                                                    C* __restrict__ snap, double* __restrict__ part) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+//   sum (theta - theta_snap)^2, sum theta^2 and max|u| into part[lb].
+template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
+__device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state, C* __restrict__ snap,
+                                           double* __restrict__ part, int lb) {
+  const int n = lb * blockDim.x + threadIdx.x;
   double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (n < kp.n) {
-    const int x = n % kp.nx;
-    const int yz = n / kp.nx;
-    const int y = yz % kp.ny;
-    const int z = yz / kp.ny;
+    int x, y, z;
+    node_coords(kp, n, x, y, z);
     const Nbr nb = make_nbr(kp, x, y, z);
     C h[Lat::Q], p[7];
-    gather<Lat, ODD, S, C>(kp, state, n, nb, h, p);
+    gather<Lat, ODD, GEN, S, C>(kp, state, n, nb, h, p);
     const Macro<C> M = macro<Lat, C>(kp, h, p);
+    LBM_GLOBAL C* sn = gbl(snap);
     if constexpr (MODE == kModeSnapshot) {
-      snap[n] = M.ux;
-      snap[n + kp.n] = M.uy;
-      snap[n + 2 * kp.n] = M.uz;
-      snap[n + 3 * kp.n] = M.T;
+      sn[n] = M.ux;
+      sn[n + kp.n] = M.uy;
+      sn[n + 2 * kp.n] = M.uz;
+      sn[n + 3 * kp.n] = M.T;
     }
     if constexpr (MODE == kModeCompare) {
       const double ux = M.ux, uy = M.uy, uz = M.uz, T = M.T;
-      const double dx = ux - (double)snap[n], dy = uy - (double)snap[n + kp.n],
-                   dz = uz - (double)snap[n + 2 * kp.n];
-      const double dT = (T - (double)snap[n + 3 * kp.n]) * (double)kp.inv_dT;
+      const double dx = ux - (double)sn[n], dy = uy - (double)sn[n + kp.n], dz = uz - (double)sn[n + 2 * kp.n];
+      const double dT = (T - (double)sn[n + 3 * kp.n]) * (double)kp.inv_dT;
       const double th = (T - (double)kp.T_ref) * (double)kp.inv_dT + 0.5;
       const double uu = ux * ux + uy * uy + uz * uz;
       red[0] = dx * dx + dy * dy + dz * dz;
@@ -272,15 +433,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const KParams<C> kp, S* __re
     }
     collide_flow<Lat, C>(kp, M, h);
     collide_heat<C>(kp, M, p);
-    scatter<Lat, ODD, S, C>(kp, state, n, nb, h, p);
+    scatter<Lat, ODD, GEN, S, C>(kp, state, n, nb, h, p, M);
   }
   if constexpr (MODE == kModeCompare) {
     block_reduce<5>(red, 1u << 4);
     if (threadIdx.x == 0) {
+      LBM_GLOBAL double* pt = gbl(part);
 #pragma unroll
-      for (int j = 0; j < 5; ++j) part[(size_t)blockIdx.x * kPartStride + j] = red[j];
+      for (int j = 0; j < 5; ++j) pt[(size_t)lb * kPartStride + j] = red[j];
     }
   }
+}
+
+// One fused time step for every node of one lattice.
+template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
+__global__ void __launch_bounds__(kMaxBlock) k_step(const KParams<C> kp, const S state,
+                                                    C* __restrict__ snap, double* __restrict__ part) {
+  step_block<Lat, S, C, ODD, MODE, GEN>(kp, state, snap, part, blockIdx.x);
 }
 
 // First stage of the two-stage reduction of per-block partials: block b folds
@@ -300,6 +469,29 @@ __global__ void __launch_bounds__(kMaxBlock) k_fold_partials(const double* __res
   }
 }
 
+// Forms the residual from the folded sums (sum|du|^2, sum|u|^2, sum dtheta^2,
+// sum theta^2, max|u|): res[0] = r, res[1] = unstable (0/1), res[2..6] = the sums;
+// res[7] (sticky) is set when unstable.
+__device__ __forceinline__ void finish_residual(const double (&v)[5], double* __restrict__ res) {
+  auto ratio = [](double num, double den) {
+    if (den > 0.0) return sqrt(num / den);
+    return num == 0.0 ? 0.0 : __builtin_inf();
+  };
+  const double ru = ratio(v[0], v[1]);
+  const double rt = ratio(v[2], v[3]);
+  double r = ru > rt ? ru : rt;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) bad = bad || !(v[j] == v[j]) || __builtin_isinf(v[j]);
+  bad = bad || v[4] > 0.5;
+  if (r != r) bad = true;
+  res[0] = r;
+  res[1] = bad ? 1.0 : 0.0;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) res[2 + j] = v[j];
+  if (bad) res[7] = 1.0;
+}
+
 // Second stage for a compare step: folds the first-stage partials and forms the
 // residual.  res[0] = r, res[1] = unstable (0/1), res[2..6] = the five totals;
 // res[7] (sticky) is set when unstable.
@@ -312,25 +504,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_residual_final(const double* __re
     v[4] = pick_max(v[4], part[(size_t)b * kPartStride + 4]);
   }
   block_reduce<5>(v, 1u << 4);
-  if (threadIdx.x == 0) {
-    auto ratio = [](double num, double den) {
-      if (den > 0.0) return sqrt(num / den);
-      return num == 0.0 ? 0.0 : __builtin_inf();
-    };
-    const double ru = ratio(v[0], v[1]);
-    const double rt = ratio(v[2], v[3]);
-    double r = ru > rt ? ru : rt;
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) bad = bad || !(v[j] == v[j]) || __builtin_isinf(v[j]);
-    bad = bad || v[4] > 0.5;
-    if (r != r) bad = true;
-    res[0] = r;
-    res[1] = bad ? 1.0 : 0.0;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) res[2 + j] = v[j];
-    if (bad) res[7] = 1.0;
-  }
+  if (threadIdx.x == 0) finish_residual(v, res);
 }
 
 // ------------------------------------------------------------------ init
@@ -347,15 +521,19 @@ struct InitArgs {
   double T_lo, T_hi;
   uint64_t seed;
   double noise_amp;
+  double u[3];
 };
 
-// Rest state f = f^eq(rho0, 0) (h = 0) and g = g^eq(T, 0) = omega_k sigma T
-// (Eq. 42), T linear along init_axis plus counter-based uniform noise.
+// Initial state f = f^eq(rho0, u0) (Eq. 24 / 18) and g = g^eq(T, u0) (Eq. 42),
+// T linear along init_axis plus counter-based uniform noise, stored shifted:
+// h_i = w_i rho0 [e.u/cs^2 + (e.u)^2/(2 phi cs^4) - u^2/(2 phi cs^2)],
+// p_k = omega_k [sigma (T - T_ref) + T e.u / csT^2].
 template <class Lat, class S, class C>
-__global__ void __launch_bounds__(kMaxBlock) k_init(const KParams<C> kp, const InitArgs ia, S* __restrict__ state) {
+__global__ void __launch_bounds__(kMaxBlock) k_init(const KParams<C> kp, const InitArgs ia, const S state) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
-  const int c[3] = {n % kp.nx, (n / kp.nx) % kp.ny, n / kp.nxy};
+  int c[3];
+  node_coords(kp, n, c[0], c[1], c[2]);
   const int dim[3] = {kp.nx, kp.ny, kp.nz};
   double T = (double)kp.T_ref;
   if (ia.init_axis >= 0) {
@@ -365,26 +543,39 @@ __global__ void __launch_bounds__(kMaxBlock) k_init(const KParams<C> kp, const I
   const double r = (double)(splitmix64(ia.seed ^ (uint64_t)n) >> 11) * (1.0 / 9007199254740992.0);
   const double noise = ia.noise_amp * (2.0 * r - 1.0);
   T = T + noise;
-  S* f = state;
-  S* g = state + (size_t)Lat::Q * kp.pstride;
-  for (int i = 0; i < Lat::Q; ++i) st<S, C>(f + (size_t)i * kp.pstride + n, C(0));
+  const uint32_t ps = (uint32_t)kp.pstride;
+  const double phi = (double)kp.phi;
+  const double uu = ia.u[0] * ia.u[0] + ia.u[1] * ia.u[1] + ia.u[2] * ia.u[2];
+  static_for<0, Lat::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const double eu = Lat::e(0, i) * ia.u[0] + Lat::e(1, i) * ia.u[1] + Lat::e(2, i) * ia.u[2];
+    const double v = weight<Lat, i>() * (3.0 * eu + 4.5 * eu * eu / phi - 1.5 * uu / phi);
+    if constexpr (i == 0) st_rs<S, C>(state, (uint32_t)n, C(v));
+    else st_mf<S, C>(state, fplane<Lat>(i) * ps + (uint32_t)n, C(v));
+  });
   const double dsT = (double)kp.sigma * (T - (double)kp.T_ref);
   const double vp = (double)kp.varpi;
-  st<S, C>(g + n, C((1.0 - vp) * dsT));
-  for (int k = 1; k < 7; ++k) st<S, C>(g + (size_t)k * kp.pstride + n, C(vp / 6.0 * dsT));
+  const double csT2 = vp / 3.0;
+  st_rs<S, C>(state, ps + (uint32_t)n, C((1.0 - vp) * dsT));
+  static_for<1, 7>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    const double eu = D3Q7::e(0, k) * ia.u[0] + D3Q7::e(1, k) * ia.u[1] + D3Q7::e(2, k) * ia.u[2];
+    st_mg<S, C>(state, gplane<Lat>(k) * ps + (uint32_t)n, C(vp / 6.0 * (dsT + T * eu / csT2)));
+  });
 }
 
 // ------------------------------------------------------------------ fields
 template <class Lat, class S, class C, bool ODD>
-__global__ void __launch_bounds__(kMaxBlock) k_fields(const KParams<C> kp, const S* __restrict__ state,
+__global__ void __launch_bounds__(kMaxBlock) k_fields(const KParams<C> kp, const S state,
                                                       double* rho, double* ux, double* uy, double* uz,
                                                       double* T) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
-  const int x = n % kp.nx, yz = n / kp.nx, y = yz % kp.ny, z = yz / kp.ny;
+  int x, y, z;
+  node_coords(kp, n, x, y, z);
   const Nbr nb = make_nbr(kp, x, y, z);
   C h[Lat::Q], p[7];
-  gather<Lat, ODD, S, C>(kp, state, n, nb, h, p);
+  gather<Lat, ODD, true, S, C>(kp, state, n, nb, h, p);
   const Macro<C> M = macro<Lat, C>(kp, h, p);
   if (rho) rho[n] = 1.0 + (double)M.drho;
   if (ux) ux[n] = (double)M.ux;
@@ -395,15 +586,16 @@ __global__ void __launch_bounds__(kMaxBlock) k_fields(const KParams<C> kp, const
 
 // Per-block FP64 sums of (rho - rho0) and sigma (T - T_ref) of the current state.
 template <class Lat, class S, class C, bool ODD>
-__global__ void __launch_bounds__(kMaxBlock) k_totals(const KParams<C> kp, const S* __restrict__ state,
+__global__ void __launch_bounds__(kMaxBlock) k_totals(const KParams<C> kp, const S state,
                                                       double* __restrict__ part) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (n < kp.n) {
-    const int x = n % kp.nx, yz = n / kp.nx, y = yz % kp.ny, z = yz / kp.ny;
+    int x, y, z;
+    node_coords(kp, n, x, y, z);
     const Nbr nb = make_nbr(kp, x, y, z);
     C h[Lat::Q], p[7];
-    gather<Lat, ODD, S, C>(kp, state, n, nb, h, p);
+    gather<Lat, ODD, true, S, C>(kp, state, n, nb, h, p);
     for (int i = 0; i < Lat::Q; ++i) v[0] += (double)h[i];
     for (int k = 0; k < 7; ++k) v[1] += (double)p[k];
   }
@@ -433,7 +625,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_sum_final(const double* __restric
 // one block per face, FP64 sum of 2 g_k - 2 omega_k sigma T_w over the face's
 // wall nodes, k the population entering the fluid.  out[face] = that sum.
 template <class Lat, class S, class C, bool ODD>
-__global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, const S* __restrict__ state,
+__global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, const S state,
                                                          const int* __restrict__ isothermal,
                                                          const double* __restrict__ T_wall,
                                                          double* __restrict__ out) {
@@ -447,7 +639,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, co
     const int k = 1 + 2 * a + side;  // D3Q7 direction pointing into the fluid
     const double w = (double)kp.varpi / 6.0;
     const double shift = 2.0 * w * (double)kp.sigma * (T_wall[face] - (double)kp.T_ref);
-    const S* g = state + (size_t)Lat::Q * kp.pstride;
+    const uint32_t gk = gplane<Lat>(k) * (uint32_t)kp.pstride;
     for (int m = threadIdx.x; m < cnt; m += blockDim.x) {
       int c[3];
       c[a] = side ? dim[a] - 1 : 0;
@@ -456,10 +648,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, co
       const int n = c[0] + kp.nx * (c[1] + kp.ny * c[2]);
       double pk;
       if (!ODD) {
-        pk = (double)ld<S, C>(g + (size_t)k * kp.pstride + n);
+        pk = (double)ld_mg<S, C>(state, gk + (uint32_t)n);
       } else {
         // the population enters from outside: anti-bounce-back of slot k of this node
-        pk = (double)(kp.heat_a[face] * ld<S, C>(g + (size_t)k * kp.pstride + n) + kp.heat_b[face]);
+        pk = (double)(kp.heat_a[face] * ld_mg<S, C>(state, gk + (uint32_t)n) + kp.heat_b[face]);
       }
       v[0] += 2.0 * pk - shift;
     }
@@ -470,21 +662,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, co
 
 // ------------------------------------------------------------------ state I/O
 template <class Lat, class S, class C, bool ODD>
-__global__ void __launch_bounds__(kMaxBlock) k_get_state(const KParams<C> kp, const S* __restrict__ state,
+__global__ void __launch_bounds__(kMaxBlock) k_get_state(const KParams<C> kp, const S state,
                                                          double* f_out, double* g_out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
-  const int x = n % kp.nx, yz = n / kp.nx, y = yz % kp.ny, z = yz / kp.ny;
+  int x, y, z;
+  node_coords(kp, n, x, y, z);
   const Nbr nb = make_nbr(kp, x, y, z);
   C h[Lat::Q], p[7];
-  gather<Lat, ODD, S, C>(kp, state, n, nb, h, p);
+  gather<Lat, ODD, true, S, C>(kp, state, n, nb, h, p);
   if (f_out) {
     static_for<0, Lat::Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      double w;
-      if constexpr (Lat::Q == 19) w = Lat::w36(i) / 36.0;
-      else w = Lat::w72(i) / 72.0;
-      f_out[(size_t)i * kp.n + n] = (double)h[i] + w;
+      f_out[(size_t)i * kp.n + n] = (double)h[i] + weight<Lat, i>();
     });
   }
   if (g_out) {
@@ -497,23 +687,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_get_state(const KParams<C> kp, co
 }
 
 template <class Lat, class S, class C>
-__global__ void __launch_bounds__(kMaxBlock) k_set_state(const KParams<C> kp, S* __restrict__ state,
+__global__ void __launch_bounds__(kMaxBlock) k_set_state(const KParams<C> kp, const S state,
                                                          const double* f_in, const double* g_in) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
-  S* f = state;
-  S* g = state + (size_t)Lat::Q * kp.pstride;
+  const uint32_t ps = (uint32_t)kp.pstride;
   static_for<0, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    double w;
-    if constexpr (Lat::Q == 19) w = Lat::w36(i) / 36.0;
-    else w = Lat::w72(i) / 72.0;
-    st<S, C>(f + (size_t)i * kp.pstride + n, C(f_in[(size_t)i * kp.n + n] - w));
+    const C v = C(f_in[(size_t)i * kp.n + n] - weight<Lat, i>());
+    if constexpr (i == 0) st_rs<S, C>(state, (uint32_t)n, v);
+    else st_mf<S, C>(state, fplane<Lat>(i) * ps + (uint32_t)n, v);
   });
   const double vp = (double)kp.varpi, sT = (double)kp.sigma * (double)kp.T_ref;
   for (int k = 0; k < 7; ++k) {
     const double om = k == 0 ? 1.0 - vp : vp / 6.0;
-    st<S, C>(g + (size_t)k * kp.pstride + n, C(g_in[(size_t)k * kp.n + n] - om * sT));
+    const C v = C(g_in[(size_t)k * kp.n + n] - om * sT);
+    if (k == 0) st_rs<S, C>(state, ps + (uint32_t)n, v);
+    else st_mg<S, C>(state, gplane<Lat>(k) * ps + (uint32_t)n, v);
   }
 }
 

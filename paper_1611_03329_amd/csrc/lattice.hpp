@@ -24,6 +24,23 @@ __host__ __device__ __forceinline__ constexpr void static_for(F&& f) {
   }
 }
 
+// Moment rows are even or odd under e -> -e; a direction i >= 1 whose opposite
+// has a larger index represents its pair.
+template <class Lat>
+constexpr bool row_is_even(int k) {
+  for (int i = 0; i < Lat::Q; ++i)
+    if (Lat::moment(k, Lat::opp(i)) != Lat::moment(k, i)) return false;
+  return true;
+}
+template <class Lat>
+constexpr bool row_is_odd(int k) {
+  for (int i = 0; i < Lat::Q; ++i)
+    if (Lat::moment(k, Lat::opp(i)) != -Lat::moment(k, i)) return false;
+  return true;
+}
+template <class Lat>
+constexpr bool is_pair_rep(int i) { return i >= 1 && Lat::opp(i) > i; }
+
 // ---------------------------------------------------------------- D3Q19
 struct D3Q19 {
   static constexpr int Q = 19;
@@ -196,7 +213,15 @@ constexpr bool check_d3q7() {
     }
   return true;
 }
+template <class Lat>
+constexpr bool every_row_has_parity() {
+  for (int k = 0; k < Lat::Q; ++k)
+    if (!row_is_even<Lat>(k) && !row_is_odd<Lat>(k)) return false;
+  return true;
+}
 static_assert(check_d3q19(), "D3Q19 moment basis does not reproduce Eq. A2");
+static_assert(every_row_has_parity<D3Q19>() && every_row_has_parity<D3Q15>(),
+              "a moment row is neither even nor odd");
 static_assert(check_d3q15(), "D3Q15 moment basis does not reproduce Eq. A1");
 static_assert(check_d3q7(), "N times the printed inverse is not the identity");
 }  // namespace detail

@@ -12,7 +12,11 @@
 #include <string>
 
 #include "lbm.h"
+#include "batch.hpp"
 #include "kernels.hpp"
+
+#include <algorithm>
+#include <vector>
 
 using namespace lbm;
 
@@ -53,7 +57,9 @@ struct lbm_lattice {
   int block = 256;
   int nblocks = 0;
   // carve-up of the device buffer
-  void* state = nullptr;
+  void* mf = nullptr;  // moving flow populations
+  void* mg = nullptr;  // moving temperature populations
+  void* rs = nullptr;  // rest populations
   void* snap = nullptr;
   double* part = nullptr;
   double* part2 = nullptr;  // first-stage fold of part
@@ -69,7 +75,10 @@ struct lbm_lattice {
   int64_t last_check = -1;
   KParams<double> kd;
   KParams<float> kf;
+  lbm_batch* batch = nullptr;  // the batch the lattice belongs to, if any
 };
+
+static lbm_status batch_pull(lbm_batch* b);
 
 static constexpr double kCs2 = 1.0 / 3.0;
 
@@ -121,13 +130,21 @@ static lbm_status derive(const lbm_params* p, lbm_derived* d) {
   if (!p || !d) return fail(LBM_ERR_INVALID_ARG, "null parameter pointer");
   if (p->lattice != 19 && p->lattice != 15)
     return fail(LBM_ERR_INVALID_ARG, "lattice must be 19 or 15 (got %d)", p->lattice);
-  if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32 && p->precision != LBM_FP16_STORAGE)
     return fail(LBM_ERR_UNSUPPORTED, "precision %d is not supported", p->precision);
   if (p->nx < 1 || p->ny < 1 || p->nz < 1)
     return fail(LBM_ERR_INVALID_ARG, "box %dx%dx%d must have at least one node per axis", p->nx, p->ny, p->nz);
   const long long nodes = (long long)p->nx * p->ny * p->nz;
   if (nodes > (1ll << 30))
     return fail(LBM_ERR_INVALID_ARG, "box of %lld nodes exceeds the 2^30 node limit", nodes);
+  {
+    const long long sb = p->precision == LBM_FP64 ? 8 : (p->precision == LBM_FP32 ? 4 : 2);
+    const long long sg = p->precision == LBM_FP64 ? 8 : 4;
+    const long long per_plane = (nodes + 127) / 128 * 128;
+    if ((long long)(p->lattice - 1) * per_plane * sb >= (1ll << 32) || 6ll * per_plane * sg >= (1ll << 32))
+      return fail(LBM_ERR_UNSUPPORTED, "each population region of one lattice must fit in 4 GiB (%lld nodes)",
+                  nodes);
+  }
   if (!(p->porosity > 0.0 && p->porosity <= 1.0)) return fail(LBM_ERR_INVALID_ARG, "porosity must be in (0,1]");
   if (!(p->darcy > 0.0) || !is_finite(p->darcy)) return fail(LBM_ERR_INVALID_ARG, "darcy must be > 0");
   if (!(p->prandtl > 0.0) || !is_finite(p->prandtl)) return fail(LBM_ERR_INVALID_ARG, "prandtl must be > 0");
@@ -144,10 +161,13 @@ static lbm_status derive(const lbm_params* p, lbm_derived* d) {
     const lbm_face& lo = p->face[2 * a];
     const lbm_face& hi = p->face[2 * a + 1];
     for (const lbm_face* f : {&lo, &hi}) {
-      if (f->flow != LBM_FLOW_PERIODIC && f->flow != LBM_FLOW_WALL)
+      if (f->flow != LBM_FLOW_PERIODIC && f->flow != LBM_FLOW_WALL && f->flow != LBM_FLOW_OUTLET)
         return fail(LBM_ERR_UNSUPPORTED, "flow rule %d is not supported", f->flow);
-      if (f->heat != LBM_HEAT_PERIODIC && f->heat != LBM_HEAT_ADIABATIC && f->heat != LBM_HEAT_ISOTHERMAL)
+      if (f->heat != LBM_HEAT_PERIODIC && f->heat != LBM_HEAT_ADIABATIC && f->heat != LBM_HEAT_ISOTHERMAL &&
+          f->heat != LBM_HEAT_OUTFLOW)
         return fail(LBM_ERR_UNSUPPORTED, "heat rule %d is not supported", f->heat);
+      for (int a2 = 0; a2 < 3; ++a2)
+        if (!is_finite(f->u_wall[a2])) return fail(LBM_ERR_INVALID_ARG, "wall velocity must be finite");
       if ((f->flow == LBM_FLOW_PERIODIC) != (f->heat == LBM_HEAT_PERIODIC))
         return fail(LBM_ERR_INVALID_ARG, "a face must be periodic for both flow and heat, or for neither");
     }
@@ -199,10 +219,14 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
   k->ny = p->ny;
   k->nz = p->nz;
   k->nxy = p->nx * p->ny;
+  k->inv_nx = std::nextafter(1.0 / p->nx, 2.0);
+  k->inv_nxy = std::nextafter(1.0 / ((double)p->nx * p->ny), 2.0);
   k->n = nodes;
   k->pstride = pstride;
   k->gaxis = p->gravity_axis;
   k->moving = 0;
+  k->open_flow = 0;
+  k->open_heat = 0;
   for (int a = 0; a < 3; ++a) k->per[a] = p->face[2 * a].flow == LBM_FLOW_PERIODIC;
   const double w7 = p->varpi / 6.0;
   for (int f = 0; f < 6; ++f) {
@@ -211,6 +235,8 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
       k->u_wall[f][a] = (C)u;
       if (u != 0.0) k->moving = 1;
     }
+    if (p->face[f].flow == LBM_FLOW_OUTLET) k->open_flow |= 1 << f;
+    if (p->face[f].heat == LBM_HEAT_OUTFLOW) k->open_heat |= 1 << f;
     if (p->face[f].heat == LBM_HEAT_ISOTHERMAL) {
       // shifted anti-bounce-back: p_in = -p_out + 2 omega sigma (T_w - T_ref)
       k->heat_a[f] = (C)-1.0;
@@ -252,27 +278,34 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
   k->inv_dT = (C)(1.0 / p->delta_T);
 }
 
-// Device layout: [state | snapshot | partials | results | flags].
+// Device layout: [moving f | moving g | rest f, g | snapshot | partials |
+// folded partials | results | flags], every region 256-byte aligned.
 struct Layout {
-  size_t state, snap, part, part2, res, iso, Tw, total;
+  size_t mf, mg, rs, snap, part, part2, res, iso, Tw, total;
   int pstride, nblocks, block, nfold;
 };
 
 static Layout layout(const lbm_params* p) {
   Layout L;
   const long long nodes = (long long)p->nx * p->ny * p->nz;
-  const size_t s = p->precision == LBM_FP64 ? 8 : 4;
+  const size_t s = p->precision == LBM_FP64 ? 8 : (p->precision == LBM_FP32 ? 4 : 2);  // moving f
+  const size_t c = p->precision == LBM_FP64 ? 8 : 4;  // moving g, rest populations, compute type
   L.block = 256;
   L.nblocks = (int)((nodes + L.block - 1) / L.block);
   // population planes start on 256-byte boundaries
-  L.pstride = (int)align_up((size_t)nodes, 256 / s);
+  L.pstride = (int)align_up((size_t)nodes, 128);
   size_t off = 0;
-  L.state = off;
-  off += align_up((size_t)(p->lattice + 7) * L.pstride * s, 256);
+  L.mf = off;
+  off += align_up((size_t)(p->lattice - 1) * L.pstride * s, 256);
+  L.mg = off;
+  off += align_up((size_t)6 * L.pstride * c, 256);
+  L.rs = off;
+  off += align_up((size_t)2 * L.pstride * c, 256);
   L.snap = off;
-  off += align_up((size_t)4 * nodes * s, 256);
+  off += align_up((size_t)4 * nodes * c, 256);
   L.part = off;
-  off += align_up((size_t)L.nblocks * kPartStride * sizeof(double), 256);
+  // sized for the smallest block a batch may use (64 threads)
+  off += align_up((size_t)((nodes + 63) / 64) * kPartStride * sizeof(double), 256);
   L.nfold = (L.nblocks + L.block - 1) / L.block;
   L.part2 = off;
   off += align_up((size_t)L.nfold * kPartStride * sizeof(double), 256);
@@ -299,13 +332,27 @@ extern "C" lbm_status lbm_required_bytes(const lbm_params* p, size_t* bytes) {
 // ------------------------------------------------------------------ dispatch
 template <class F>
 static void with_types(const lbm_lattice* h, F&& f) {
+  using S64 = Store<double, double, double>;
+  using S32 = Store<float, float, float>;
+  using S16 = Store<_Float16, float, float>;
   if (h->q == 19) {
-    if (h->prec == LBM_FP64) f(D3Q19{}, double{}, double{}, h->kd);
-    else f(D3Q19{}, float{}, float{}, h->kf);
+    if (h->prec == LBM_FP64) f(D3Q19{}, S64{}, double{}, h->kd);
+    else if (h->prec == LBM_FP32) f(D3Q19{}, S32{}, float{}, h->kf);
+    else f(D3Q19{}, S16{}, float{}, h->kf);
   } else {
-    if (h->prec == LBM_FP64) f(D3Q15{}, double{}, double{}, h->kd);
-    else f(D3Q15{}, float{}, float{}, h->kf);
+    if (h->prec == LBM_FP64) f(D3Q15{}, S64{}, double{}, h->kd);
+    else if (h->prec == LBM_FP32) f(D3Q15{}, S32{}, float{}, h->kf);
+    else f(D3Q15{}, S16{}, float{}, h->kf);
   }
+}
+
+template <class S>
+static S make_store(const lbm_lattice* h) {
+  S s;
+  s.mf = static_cast<typename S::MoveF*>(h->mf);
+  s.mg = static_cast<typename S::MoveG*>(h->mg);
+  s.rs = static_cast<typename S::Rest*>(h->rs);
+  return s;
 }
 
 static lbm_status launch_check(const char* what) {
@@ -359,7 +406,9 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   }
   std::memset(h->host_res, 0, 32 * sizeof(double));
   char* base = static_cast<char*>(h->buf);
-  h->state = base + L.state;
+  h->mf = base + L.mf;
+  h->mg = base + L.mg;
+  h->rs = base + L.rs;
   h->snap = base + L.snap;
   h->part = reinterpret_cast<double*>(base + L.part);
   h->part2 = reinterpret_cast<double*>(base + L.part2);
@@ -388,13 +437,14 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
     cleanup();
     return fail(LBM_ERR_DEVICE, "initial copies failed");
   }
-  InitArgs ia{p->init_axis, p->init_T_lo, p->init_T_hi, p->seed, p->noise_amp};
+  InitArgs ia{p->init_axis, p->init_T_lo, p->init_T_hi, p->seed, p->noise_amp,
+              {p->init_u[0], p->init_u[1], p->init_u[2]}};
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
     hipLaunchKernelGGL((k_init<Lat, S, C>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, ia,
-                       static_cast<S*>(h->state));
+                       make_store<S>(h));
   });
   st_ = launch_check("init");
   if (st_ != LBM_OK) {
@@ -413,6 +463,7 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
 extern "C" lbm_status lbm_destroy(lbm_lattice* h) {
   if (!h) return LBM_OK;
   lbm_status s = LBM_OK;
+  if (h->batch) s = lbm_batch_remove(h->batch, h);
   if (hipStreamSynchronize(h->stream) != hipSuccess) s = fail(LBM_ERR_DEVICE, "stream synchronize failed");
   (void)hipHostFree(h->host_res);
   if (h->owns_buf) (void)hipFree(h->buf);
@@ -422,6 +473,7 @@ extern "C" lbm_status lbm_destroy(lbm_lattice* h) {
 
 extern "C" lbm_status lbm_set_stream(lbm_lattice* h, void* stream) {
   if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
+  if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice is in a batch and uses the batch's stream");
   h->stream = (hipStream_t)stream;
   return LBM_OK;
 }
@@ -439,25 +491,37 @@ extern "C" lbm_status lbm_derived_params(const lbm_lattice* h, lbm_derived* d) {
 }
 
 // ------------------------------------------------------------------ step
-template <class Lat, class S, class C>
-static void launch_step(lbm_lattice* h, const KParams<C>& kp, int mode) {
-  S* st_ = static_cast<S*>(h->state);
+template <class Lat, class S, class C, bool ODD, bool GEN>
+static void launch_step_mode(lbm_lattice* h, const KParams<C>& kp, int mode) {
+  const S st_ = make_store<S>(h);
   C* sn = static_cast<C*>(h->snap);
   const dim3 g(h->nblocks), b(h->block);
+  if (mode == kModePlain)
+    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModePlain, GEN>), g, b, 0, h->stream, kp, st_, sn, h->part);
+  else if (mode == kModeSnapshot)
+    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModeSnapshot, GEN>), g, b, 0, h->stream, kp, st_, sn, h->part);
+  else
+    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModeCompare, GEN>), g, b, 0, h->stream, kp, st_, sn, h->part);
+}
+
+// GEN (moving walls or open faces present) selects the kernels that compile
+// those rules; boxes with only periodic faces and static walls use the lean ones.
+template <class Lat, class S, class C>
+static void launch_step(lbm_lattice* h, const KParams<C>& kp, int mode) {
+  const bool gen = kp.moving || kp.open_flow || kp.open_heat;
   if (h->parity == 0) {
-    if (mode == kModePlain) hipLaunchKernelGGL((k_step<Lat, S, C, false, kModePlain>), g, b, 0, h->stream, kp, st_, sn, h->part);
-    else if (mode == kModeSnapshot) hipLaunchKernelGGL((k_step<Lat, S, C, false, kModeSnapshot>), g, b, 0, h->stream, kp, st_, sn, h->part);
-    else hipLaunchKernelGGL((k_step<Lat, S, C, false, kModeCompare>), g, b, 0, h->stream, kp, st_, sn, h->part);
+    if (gen) launch_step_mode<Lat, S, C, false, true>(h, kp, mode);
+    else launch_step_mode<Lat, S, C, false, false>(h, kp, mode);
   } else {
-    if (mode == kModePlain) hipLaunchKernelGGL((k_step<Lat, S, C, true, kModePlain>), g, b, 0, h->stream, kp, st_, sn, h->part);
-    else if (mode == kModeSnapshot) hipLaunchKernelGGL((k_step<Lat, S, C, true, kModeSnapshot>), g, b, 0, h->stream, kp, st_, sn, h->part);
-    else hipLaunchKernelGGL((k_step<Lat, S, C, true, kModeCompare>), g, b, 0, h->stream, kp, st_, sn, h->part);
+    if (gen) launch_step_mode<Lat, S, C, true, true>(h, kp, mode);
+    else launch_step_mode<Lat, S, C, true, false>(h, kp, mode);
   }
 }
 
 extern "C" lbm_status lbm_step(lbm_lattice* h, int64_t nsteps) {
   if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
   if (nsteps < 0) return fail(LBM_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice is in a batch: step the batch");
   if (h->host_res[7] != 0.0) return fail(LBM_ERR_UNSTABLE, "lattice was found unstable at an earlier check");
   const int64_t K = h->p.check_interval;
   for (int64_t s = 0; s < nsteps; ++s) {
@@ -499,7 +563,7 @@ extern "C" lbm_status lbm_fields(lbm_lattice* h, double* rho, double* ux, double
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
-    const S* st_ = static_cast<const S*>(h->state);
+    const S st_ = make_store<S>(h);
     if (h->parity)
       hipLaunchKernelGGL((k_fields<Lat, S, C, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, rho, ux, uy, uz, T);
     else
@@ -514,7 +578,7 @@ extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
-    const S* st_ = static_cast<const S*>(h->state);
+    const S st_ = make_store<S>(h);
     if (h->parity)
       hipLaunchKernelGGL((k_wall_flux<Lat, S, C, true>), dim3(6), dim3(256), 0, h->stream, kp, st_, h->dev_iso, h->dev_Tw, h->res + 8);
     else
@@ -537,6 +601,10 @@ extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {
 
 extern "C" lbm_status lbm_residual(lbm_lattice* h, double* r, int64_t* at_step) {
   if (!h || !r || !at_step) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (h->batch) {
+    lbm_status st_ = batch_pull(h->batch);
+    if (st_ != LBM_OK) return st_;
+  }
   HIP_TRY(hipStreamSynchronize(h->stream));
   if (h->last_check < 0) {
     *r = -1.0;
@@ -555,7 +623,7 @@ extern "C" lbm_status lbm_totals(lbm_lattice* h, double* mass, double* heat) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
-    const S* st_ = static_cast<const S*>(h->state);
+    const S st_ = make_store<S>(h);
     if (h->parity)
       hipLaunchKernelGGL((k_totals<Lat, S, C, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, h->part);
     else
@@ -582,7 +650,7 @@ extern "C" lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
-    const S* st_ = static_cast<const S*>(h->state);
+    const S st_ = make_store<S>(h);
     if (h->parity)
       hipLaunchKernelGGL((k_get_state<Lat, S, C, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, f, g);
     else
@@ -593,18 +661,544 @@ extern "C" lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g) {
 
 extern "C" lbm_status lbm_set_state(lbm_lattice* h, const double* f, const double* g) {
   if (!h || !f || !g) return fail(LBM_ERR_INVALID_ARG, "lbm_set_state needs both f and g");
+  if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice is in a batch: remove it first");
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
     hipLaunchKernelGGL((k_set_state<Lat, S, C>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp,
-                       static_cast<S*>(h->state), f, g);
+                       make_store<S>(h), f, g);
   });
   lbm_status ls = launch_check("set_state");
   if (ls != LBM_OK) return ls;
   h->parity = 0;
   h->snapshot_valid = false;
   return LBM_OK;
+}
+
+// ------------------------------------------------------------------ batches
+// A batch advances its member lattices together, one launch per time step (two
+// when members need both the lean and the general wall rules).  Members share
+// the lattice type, precision, stream and time parity.  The residual check runs
+// on the batch's own schedule: batch step s snapshots when (s + 1) % K == 0 and
+// compares when s % K == 0, s > 0; a member compares only once it has taken a
+// snapshot inside the batch.
+struct lbm_batch {
+  hipStream_t stream = nullptr;
+  int q = 0, prec = -1;
+  int check = 0;
+  int block = 256;     // threads per tile
+  int per_cu = 0;      // resident blocks per compute unit (persistent launch); 0: one block per tile
+  int ncu = 0;         // compute units of the device
+  int64_t s = 0;
+  int parity = 0;
+  bool use_graph = false;
+  std::vector<lbm_lattice*> members;  // join order
+  std::vector<int> compare_ok;        // the member holds a snapshot for the next compare
+  std::vector<int64_t> last_check;    // lattice time of the member's last compare
+  std::vector<int> fresh;             // a result row not yet pulled into the member
+  // device descriptors, per group (0: lean rules, 1: general rules)
+  void* dev_mem[2] = {nullptr, nullptr};
+  size_t dev_cap[2] = {0, 0};
+  int count[2] = {0, 0};
+  int blocks[2] = {0, 0};
+  std::vector<int> slot;  // member index -> row of out (group 0 rows first)
+  double* dev_out = nullptr;
+  double* host_out = nullptr;
+  size_t out_cap = 0;
+  void* staging = nullptr;  // pinned upload buffer
+  size_t staging_cap = 0;
+  hipEvent_t staged = nullptr;
+  bool dirty = true;
+  // a captured chunk of K steps starting at a compare step, per start parity
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // what the captured launches depend on besides the descriptors' contents
+  struct Key {
+    const void* mem[2];
+    int count[2], tiles[2], block, grid[2];
+    const double* out;
+    const double* host;
+    bool operator==(const Key& o) const { return std::memcmp(this, &o, sizeof(Key)) == 0; }
+  } key{};
+};
+
+static int batch_grid(const lbm_batch* b, int grp) {
+  const int tiles = b->blocks[grp];
+  return b->per_cu > 0 ? std::min(tiles, b->per_cu * std::max(b->ncu, 1)) : tiles;
+}
+
+static bool member_general(const lbm_lattice* h) {
+  return h->kd.moving || h->kd.open_flow || h->kd.open_heat;
+}
+
+static void batch_drop_graphs(lbm_batch* b) {
+  for (auto& g : b->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Waits for the batch's stream and moves every new result row into its member's
+// own host mirror (the rows are laid out by the current descriptors).
+static lbm_status batch_pull(lbm_batch* b) {
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    if (!b->fresh[i]) continue;
+    lbm_lattice* h = b->members[i];
+    std::memcpy(h->host_res, b->host_out + (size_t)b->slot[i] * kPartStride, 8 * sizeof(double));
+    h->last_check = b->last_check[i];
+    b->fresh[i] = 0;
+  }
+  return LBM_OK;
+}
+
+static const KParams<double>& kp_of(const lbm_lattice* h, double) { return h->kd; }
+static const KParams<float>& kp_of(const lbm_lattice* h, float) { return h->kf; }
+
+template <class S, class C>
+static void fill_members(const lbm_batch* b, int grp, std::vector<Member<S, C>>& out) {
+  out.clear();
+  int block0 = 0;
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    lbm_lattice* h = b->members[i];
+    if ((int)member_general(h) != grp) continue;
+    Member<S, C> m;
+    std::memset(&m, 0, sizeof(m));
+    m.kp = kp_of(h, C{});
+    m.sto = make_store<S>(h);
+    m.snap = static_cast<C*>(h->snap);
+    m.part = h->part;
+    m.res = h->res;
+    m.block0 = block0;
+    m.nblocks = (h->nodes + b->block - 1) / b->block;
+    m.check = b->compare_ok[i];
+    block0 += m.nblocks;
+    out.push_back(m);
+  }
+}
+
+// Rebuilds both descriptor groups and uploads them (stream-ordered copies from
+// pinned staging).  Pending result rows are pulled first: the rows move.
+template <class S, class C>
+static lbm_status batch_upload_typed(lbm_batch* b) {
+  lbm_status st_ = batch_pull(b);
+  if (st_ != LBM_OK) return st_;
+  std::vector<Member<S, C>> g[2];
+  fill_members<S, C>(b, 0, g[0]);
+  fill_members<S, C>(b, 1, g[1]);
+  const size_t need = (g[0].size() + g[1].size()) * sizeof(Member<S, C>);
+  if (need > b->staging_cap) {
+    if (b->staging) (void)hipHostFree(b->staging);
+    b->staging = nullptr;
+    b->staging_cap = 0;
+    HIP_TRY(hipHostMalloc(&b->staging, need, hipHostMallocDefault));
+    b->staging_cap = need;
+  }
+  char* stage = static_cast<char*>(b->staging);
+  size_t off = 0;
+  b->slot.assign(b->members.size(), 0);
+  int row = 0;
+  for (int grp = 0; grp < 2; ++grp) {
+    const size_t bytes = g[grp].size() * sizeof(Member<S, C>);
+    if (bytes > b->dev_cap[grp]) {
+      if (b->dev_mem[grp]) (void)hipFree(b->dev_mem[grp]);
+      b->dev_mem[grp] = nullptr;
+      b->dev_cap[grp] = 0;
+      HIP_TRY(hipMalloc(&b->dev_mem[grp], bytes));
+      b->dev_cap[grp] = bytes;
+    }
+    if (bytes) {
+      std::memcpy(stage + off, g[grp].data(), bytes);
+      HIP_TRY(hipMemcpyAsync(b->dev_mem[grp], stage + off, bytes, hipMemcpyHostToDevice, b->stream));
+    }
+    off += bytes;
+    b->count[grp] = (int)g[grp].size();
+    b->blocks[grp] = g[grp].empty() ? 0 : g[grp].back().block0 + g[grp].back().nblocks;
+    for (size_t i = 0, k = 0; i < b->members.size(); ++i)
+      if ((int)member_general(b->members[i]) == grp) b->slot[i] = row + (int)(k++);
+    row += (int)g[grp].size();
+  }
+  const size_t out_need = (size_t)std::max(row, 1) * kPartStride * sizeof(double);
+  if (out_need > b->out_cap) {
+    if (b->dev_out) (void)hipFree(b->dev_out);
+    if (b->host_out) (void)hipHostFree(b->host_out);
+    b->dev_out = nullptr;
+    b->host_out = nullptr;
+    b->out_cap = 0;
+    HIP_TRY(hipMalloc((void**)&b->dev_out, out_need));
+    HIP_TRY(hipHostMalloc((void**)&b->host_out, out_need, hipHostMallocDefault));
+    std::memset(b->host_out, 0, out_need);
+    b->out_cap = out_need;
+  }
+  // the staging buffer is rewritten by the next upload only after this one landed
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->dirty = false;
+  // captured launches read the descriptors from device memory: they stay valid
+  // while the buffers, the member counts and the launch shapes are unchanged
+  lbm_batch::Key k;
+  std::memset(&k, 0, sizeof(k));
+  for (int grp = 0; grp < 2; ++grp) {
+    k.mem[grp] = b->dev_mem[grp];
+    k.count[grp] = b->count[grp];
+    k.tiles[grp] = b->blocks[grp];
+    k.grid[grp] = batch_grid(b, grp);
+  }
+  k.block = b->block;
+  k.out = b->dev_out;
+  k.host = b->host_out;
+  if (!(k == b->key)) batch_drop_graphs(b);
+  b->key = k;
+  return LBM_OK;
+}
+
+template <class F>
+static void batch_types(const lbm_batch* b, F&& f) {
+  using S64 = Store<double, double, double>;
+  using S32 = Store<float, float, float>;
+  using S16 = Store<_Float16, float, float>;
+  if (b->q == 19) {
+    if (b->prec == LBM_FP64) f(D3Q19{}, S64{}, double{});
+    else if (b->prec == LBM_FP32) f(D3Q19{}, S32{}, float{});
+    else f(D3Q19{}, S16{}, float{});
+  } else {
+    if (b->prec == LBM_FP64) f(D3Q15{}, S64{}, double{});
+    else if (b->prec == LBM_FP32) f(D3Q15{}, S32{}, float{});
+    else f(D3Q15{}, S16{}, float{});
+  }
+}
+
+static lbm_status batch_upload(lbm_batch* b) {
+  lbm_status st_ = LBM_OK;
+  batch_types(b, [&](auto, auto s_t, auto c_t) {
+    st_ = batch_upload_typed<decltype(s_t), decltype(c_t)>(b);
+  });
+  return st_;
+}
+
+template <class Lat, class S, class C, bool ODD, int MODE>
+static void batch_launch_mode(lbm_batch* b) {
+  for (int grp = 0; grp < 2; ++grp) {
+    if (!b->count[grp]) continue;
+    const auto* mem = static_cast<const Member<S, C>*>(b->dev_mem[grp]);
+    const int grid = batch_grid(b, grp);
+    if (grp == 0)
+      hipLaunchKernelGGL((k_step_batch<Lat, S, C, ODD, MODE, false>), dim3(grid), dim3(b->block), 0, b->stream,
+                         mem, b->count[grp], b->blocks[grp]);
+    else
+      hipLaunchKernelGGL((k_step_batch<Lat, S, C, ODD, MODE, true>), dim3(grid), dim3(b->block), 0, b->stream,
+                         mem, b->count[grp], b->blocks[grp]);
+  }
+}
+
+static int batch_mode(const lbm_batch* b, int64_t s) {
+  const int64_t K = b->check;
+  if (K > 0 && (s + 1) % K == 0) return kModeSnapshot;
+  if (K > 0 && s > 0 && s % K == 0) return kModeCompare;
+  return kModePlain;
+}
+
+// Enqueues batch step s with the given parity and, after a compare step, the
+// per-member folds and one copy of all result rows to the host.
+static lbm_status batch_enqueue_step(lbm_batch* b, int64_t s, int parity) {
+  const int mode = batch_mode(b, s);
+  lbm_status st_ = LBM_OK;
+  batch_types(b, [&](auto lat, auto s_t, auto c_t) {
+    using Lat = decltype(lat);
+    using S = decltype(s_t);
+    using C = decltype(c_t);
+    if (parity == 0) {
+      if (mode == kModePlain) batch_launch_mode<Lat, S, C, false, kModePlain>(b);
+      else if (mode == kModeSnapshot) batch_launch_mode<Lat, S, C, false, kModeSnapshot>(b);
+      else batch_launch_mode<Lat, S, C, false, kModeCompare>(b);
+    } else {
+      if (mode == kModePlain) batch_launch_mode<Lat, S, C, true, kModePlain>(b);
+      else if (mode == kModeSnapshot) batch_launch_mode<Lat, S, C, true, kModeSnapshot>(b);
+      else batch_launch_mode<Lat, S, C, true, kModeCompare>(b);
+    }
+    st_ = launch_check("batch step");
+    if (st_ != LBM_OK || mode != kModeCompare) return;
+    int row = 0;
+    for (int grp = 0; grp < 2; ++grp) {
+      if (b->count[grp])
+        hipLaunchKernelGGL((k_fold_members<S, C>), dim3(b->count[grp]), dim3(256), 0, b->stream,
+                           static_cast<const Member<S, C>*>(b->dev_mem[grp]), b->dev_out + (size_t)row * kPartStride);
+      row += b->count[grp];
+    }
+    st_ = launch_check("batch residual");
+    if (st_ != LBM_OK) return;
+    if (hipMemcpyAsync(b->host_out, b->dev_out, (size_t)row * kPartStride * sizeof(double), hipMemcpyDeviceToHost,
+                       b->stream) != hipSuccess)
+      st_ = fail(LBM_ERR_DEVICE, "copy of the batch residuals failed");
+  });
+  return st_;
+}
+
+// Host bookkeeping after batch step s was enqueued.
+static void batch_account(lbm_batch* b, int64_t s) {
+  const int mode = batch_mode(b, s);
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    lbm_lattice* h = b->members[i];
+    if (mode == kModeCompare && b->compare_ok[i]) {
+      b->last_check[i] = h->t;
+      b->fresh[i] = 1;
+    }
+    h->t += 1;
+    h->parity ^= 1;
+    h->snapshot_valid = false;
+  }
+  if (mode == kModeSnapshot)
+    for (size_t i = 0; i < b->members.size(); ++i)
+      if (!b->compare_ok[i]) {
+        b->compare_ok[i] = 1;
+        b->dirty = true;
+      }
+  b->s = s + 1;
+  b->parity ^= 1;
+}
+
+// Captures one chunk of K steps that starts at a compare step with parity p:
+// steps K .. 2K-1 of the schedule have the modes of every later chunk.
+static lbm_status batch_capture(lbm_batch* b, int p) {
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  lbm_status st_ = LBM_OK;
+  for (int64_t j = 0; j < b->check && st_ == LBM_OK; ++j) st_ = batch_enqueue_step(b, b->check + j, (p + (int)j) & 1);
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (st_ != LBM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st_;
+  }
+  if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  const hipError_t ei = hipGraphInstantiate(&b->graph[p], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    b->graph[p] = nullptr;
+    return fail(LBM_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_create(void* stream, int32_t check_interval, lbm_batch** out) {
+  if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (check_interval < 0) return fail(LBM_ERR_INVALID_ARG, "check_interval must be >= 0");
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return fail(LBM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  b->stream = (hipStream_t)stream;
+  b->check = check_interval;
+  *out = b;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_OK;
+  lbm_status s = LBM_OK;
+  if (b->host_out && !b->slot.empty()) s = batch_pull(b);
+  else if (hipStreamSynchronize(b->stream) != hipSuccess) s = fail(LBM_ERR_DEVICE, "stream synchronize failed");
+  for (lbm_lattice* h : b->members) h->batch = nullptr;
+  batch_drop_graphs(b);
+  for (auto& p : b->dev_mem)
+    if (p) (void)hipFree(p);
+  if (b->dev_out) (void)hipFree(b->dev_out);
+  if (b->host_out) (void)hipHostFree(b->host_out);
+  if (b->staging) (void)hipHostFree(b->staging);
+  delete b;
+  return s;
+}
+
+extern "C" lbm_status lbm_batch_add(lbm_batch* b, lbm_lattice* h) {
+  if (!b || !h) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice already belongs to a batch");
+  if (!b->members.empty() && (h->q != b->q || h->prec != b->prec))
+    return fail(LBM_ERR_UNSUPPORTED, "batch members must share the lattice type and precision");
+  if (h->stream != b->stream) {
+    // the lattice moves to the batch's stream once its own work is done
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->stream = b->stream;
+  }
+  if (b->members.empty()) {
+    b->q = h->q;
+    b->prec = h->prec;
+    b->parity = h->parity;
+  } else if (h->parity != b->parity) {
+    // one step of its own brings the lattice to the batch's parity
+    lbm_status st_ = lbm_step(h, 1);
+    if (st_ != LBM_OK) return st_;
+  }
+  h->snapshot_valid = false;
+  h->batch = b;
+  b->members.push_back(h);
+  b->compare_ok.push_back(0);
+  b->last_check.push_back(-1);
+  b->fresh.push_back(0);
+  b->dirty = true;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_remove(lbm_batch* b, lbm_lattice* h) {
+  if (!b || !h) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  auto it = std::find(b->members.begin(), b->members.end(), h);
+  if (it == b->members.end()) return fail(LBM_ERR_INVALID_ARG, "the lattice is not in the batch");
+  lbm_status st_ = batch_pull(b);
+  if (st_ != LBM_OK) return st_;
+  const size_t i = (size_t)(it - b->members.begin());
+  b->members.erase(it);
+  b->compare_ok.erase(b->compare_ok.begin() + i);
+  b->last_check.erase(b->last_check.begin() + i);
+  b->fresh.erase(b->fresh.begin() + i);
+  if (i < b->slot.size()) b->slot.erase(b->slot.begin() + i);
+  h->batch = nullptr;
+  b->dirty = true;
+  if (b->members.empty()) {
+    b->q = 0;
+    b->prec = -1;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_size(const lbm_batch* b, int32_t* count) {
+  if (!b || !count) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  *count = (int32_t)b->members.size();
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu) {
+  if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+  if (block != 64 && block != 128 && block != 256)
+    return fail(LBM_ERR_INVALID_ARG, "block must be 64, 128 or 256 (got %d)", block);
+  if (blocks_per_cu < 0 || blocks_per_cu > 64)
+    return fail(LBM_ERR_INVALID_ARG, "blocks_per_cu must be in [0, 64] (got %d)", blocks_per_cu);
+  if (blocks_per_cu > 0 && b->ncu == 0) {
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    b->ncu = ncu;
+  }
+  if (block != b->block || blocks_per_cu != b->per_cu) {
+    b->block = block;
+    b->per_cu = blocks_per_cu;
+    b->dirty = true;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_set_graph(lbm_batch* b, int32_t on) {
+  if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+  if (on && !b->stream) return fail(LBM_ERR_UNSUPPORTED, "graph replay needs a batch on a created stream, not the null stream");
+  if (on && b->check <= 0) return fail(LBM_ERR_UNSUPPORTED, "graph replay needs a check interval > 0");
+  b->use_graph = on != 0;
+  if (!b->use_graph) batch_drop_graphs(b);
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+  if (nsteps < 0) return fail(LBM_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (b->members.empty() || nsteps == 0) return LBM_OK;
+  int64_t left = nsteps;
+  while (left > 0) {
+    if (b->dirty) {
+      lbm_status st_ = batch_upload(b);
+      if (st_ != LBM_OK) return st_;
+    }
+    const int64_t K = b->check;
+    if (b->use_graph && b->s % K == 0 && left >= K) {
+      // the whole chunk [s, s + K) as one replay.  Its launches are those of
+      // steps K .. 2K-1; at s = 0 its first step compares nothing (no member has
+      // a snapshot yet: the compare kernel then steps plainly).  A member whose
+      // snapshot is taken inside the chunk gets its compare flag uploaded before
+      // the next chunk.
+      if (!b->graph[b->parity]) {
+        lbm_status st_ = batch_capture(b, b->parity);
+        if (st_ != LBM_OK) return st_;
+      }
+      HIP_TRY(hipGraphLaunch(b->graph[b->parity], b->stream));
+      for (int64_t j = 0; j < K; ++j) batch_account(b, b->s);
+      left -= K;
+      continue;
+    }
+    lbm_status st_ = batch_enqueue_step(b, b->s, b->parity);
+    if (st_ != LBM_OK) return st_;
+    batch_account(b, b->s);
+    left -= 1;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_residuals(lbm_batch* b, double* r, int64_t* at_step, int32_t* unstable,
+                                          int32_t count) {
+  if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+  if (count != (int32_t)b->members.size())
+    return fail(LBM_ERR_INVALID_ARG, "count %d differs from the %zu members", count, b->members.size());
+  lbm_status st_ = batch_pull(b);
+  if (st_ != LBM_OK) return st_;
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    const lbm_lattice* h = b->members[i];
+    const bool have = h->last_check >= 0;
+    if (r) r[i] = have ? h->host_res[0] : -1.0;
+    if (at_step) at_step[i] = have ? h->last_check : -1;
+    if (unstable) unstable[i] = h->host_res[7] != 0.0 ? 1 : 0;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_member(const lbm_batch* b, int32_t index, lbm_lattice** out) {
+  if (!b || !out) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (index < 0 || index >= (int32_t)b->members.size())
+    return fail(LBM_ERR_INVALID_ARG, "member index %d out of range", index);
+  *out = b->members[(size_t)index];
+  return LBM_OK;
+}
+
+// Times every admissible launch shape (threads per tile x resident blocks per
+// compute unit) over `steps` batch steps, after one step that absorbs the
+// descriptor upload, and keeps the fastest.  The steps are real: the members
+// advance.
+extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* block, int32_t* blocks_per_cu) {
+  if (!b || steps < 1) return fail(LBM_ERR_INVALID_ARG, "bad autotune arguments");
+  if (b->members.empty()) return fail(LBM_ERR_INVALID_ARG, "the batch is empty");
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(LBM_ERR_DEVICE, "event creation failed");
+  }
+  const int blocks[3] = {64, 128, 256};
+  const int per_cu[4] = {0, 4, 8, 16};
+  const bool graph = b->use_graph;
+  b->use_graph = false;  // time the launches themselves
+  float best = -1.0f;
+  int best_block = b->block, best_per_cu = b->per_cu;
+  lbm_status st_ = LBM_OK;
+  for (int bl : blocks) {
+    for (int pc : per_cu) {
+      if ((st_ = lbm_batch_set_launch(b, bl, pc)) != LBM_OK) break;
+      if ((st_ = lbm_batch_step(b, 1)) != LBM_OK) break;
+      (void)hipEventRecord(e0, b->stream);
+      if ((st_ = lbm_batch_step(b, steps)) != LBM_OK) break;
+      (void)hipEventRecord(e1, b->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st_ = fail(LBM_ERR_DEVICE, "event synchronize failed");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        best_block = bl;
+        best_per_cu = pc;
+      }
+    }
+    if (st_ != LBM_OK) break;
+  }
+  b->use_graph = graph;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st_ != LBM_OK) return st_;
+  if (block) *block = best_block;
+  if (blocks_per_cu) *blocks_per_cu = best_per_cu;
+  return lbm_batch_set_launch(b, best_block, best_per_cu);
 }
 
 extern "C" const char* lbm_status_string(lbm_status s) {

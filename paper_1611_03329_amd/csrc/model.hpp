@@ -18,13 +18,17 @@ template <class C>
 struct KParams {
   int nx, ny, nz;
   int nxy;          // nx * ny
+  double inv_nx;    // 1/nx and 1/(nx*ny) rounded up: exact quotients for n < 2^31
+  double inv_nxy;
   int n;            // nodes
   int pstride;      // elements between consecutive population planes
   int per[3];       // axis is periodic
   int gaxis;        // buoyancy axis
-  int moving;       // some wall face has a nonzero velocity
+  int moving;       // some wall face has a nonzero velocity (used when GEN)
+  int open_flow;    // bit f set: face f is an open outlet for f (flow)
+  int open_heat;    // bit f set: face f is an outflow face for g
   C u_wall[6][3];   // wall velocity per face
-  C heat_a[6];      // thermal wall rule: p_in = heat_a * p_out + heat_b
+  C heat_a[6];      // thermal wall rule: p_in = heat_a * p_out + heat_b (1, 0 on outflow faces)
   C heat_b[6];
   C phi, inv_phi;   // porosity
   C c_darcy;        // phi nu / K        (Eq. 4)
@@ -205,36 +209,70 @@ __device__ __forceinline__ C forcing(D3Q15, int k, const Macro<C>& M, C inv_phi)
 //   dm_k = (M h)_k - (m^eq_k - m^eq_k(rest)),
 //   delta_k = -s_k dm_k + (1 - s_k/2) S~_k,
 //   h*_i = h_i + sum_k M_ki delta_k / |M_k|^2          (M^-1 = M^T diag(1/|M_k|^2)).
-// Row 0 has dm_0 = 0 and S~_0 = 0, so it is skipped.
+// Row 0 has dm_0 = 0 and S~_0 = 0, so it is skipped.  Both products use the
+// symmetry of the basis: with s_i = h_i + h_ibar and d_i = h_i - h_ibar for one
+// direction i of each opposite pair, even rows of M see only h_0 and the s_i,
+// odd rows only the d_i; on the way back h*_i and h*_ibar share the even part
+// and differ in the sign of the odd part.
 template <class Lat, class C>
 __device__ __forceinline__ void collide_flow(const KParams<C>& kp, const Macro<C>& M, C (&h)[Lat::Q]) {
   constexpr int Q = Lat::Q;
+  C sp[Q], dp[Q];  // used at pair representatives only
+  static_for<1, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    if constexpr (is_pair_rep<Lat>(i)) {
+      sp[i] = h[i] + h[Lat::opp(i)];
+      dp[i] = h[i] - h[Lat::opp(i)];
+    }
+  });
   C d[Q];
   static_for<1, Q>([&](auto K) {
     constexpr int k = decltype(K)::value;
+    constexpr bool even = row_is_even<Lat>(k);
     C m = C(0);
-    static_for<0, Q>([&](auto I) {
+    if constexpr (even && Lat::moment(k, 0) != 0) m = C(Lat::moment(k, 0)) * h[0];
+    static_for<1, Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      constexpr int c = Lat::moment(k, i);
-      if constexpr (c == 1) m += h[i];
-      else if constexpr (c == -1) m -= h[i];
-      else if constexpr (c != 0) m += C(c) * h[i];
+      if constexpr (is_pair_rep<Lat>(i)) {
+        constexpr int c = Lat::moment(k, i);
+        const C v = even ? sp[i] : dp[i];
+        if constexpr (c == 1) m += v;
+        else if constexpr (c == -1) m -= v;
+        else if constexpr (c != 0) m += C(c) * v;
+      }
     });
     const C dm = m - meq_shift(Lat{}, k, M, kp.inv_phi);
     const C delta = -kp.s[k] * dm + kp.sh[k] * forcing(Lat{}, k, M, kp.inv_phi);
     d[k] = delta * C(1.0 / Lat::norm2(k));
   });
-  static_for<0, Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    C acc = h[i];
+  // rest population: even rows only
+  {
+    C acc = h[0];
     static_for<1, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      constexpr int c = Lat::moment(k, i);
-      if constexpr (c == 1) acc += d[k];
-      else if constexpr (c == -1) acc -= d[k];
-      else if constexpr (c != 0) acc += C(c) * d[k];
+      constexpr int c = Lat::moment(k, 0);
+      if constexpr (row_is_even<Lat>(k) && c != 0) acc += C(c) * d[k];
     });
-    h[i] = acc;
+    h[0] = acc;
+  }
+  static_for<1, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    if constexpr (is_pair_rep<Lat>(i)) {
+      C ev = C(0), od = C(0);
+      static_for<1, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr int c = Lat::moment(k, i);
+        if constexpr (c != 0) {
+          C& acc = row_is_even<Lat>(k) ? ev : od;
+          if constexpr (c == 1) acc += d[k];
+          else if constexpr (c == -1) acc -= d[k];
+          else acc += C(c) * d[k];
+        }
+      });
+      constexpr int io = Lat::opp(i);
+      h[io] = h[io] + (ev - od);
+      h[i] = h[i] + (ev + od);
+    }
   });
 }
 

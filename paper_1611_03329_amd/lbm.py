@@ -24,9 +24,10 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 FP64 = 0
 FP32 = 1
-PRECISIONS = {"fp64": FP64, "fp32": FP32}
-FLOW = {"periodic": 0, "wall": 1}
-HEAT = {"periodic": 0, "adiabatic": 1, "isothermal": 2}
+FP16_STORAGE = 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_STORAGE}
+FLOW = {"periodic": 0, "wall": 1, "outlet": 3}
+HEAT = {"periodic": 0, "adiabatic": 1, "isothermal": 2, "outflow": 3}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error",
           4: "unstable", 5: "unsupported"}
 
@@ -69,6 +70,7 @@ class Params(ctypes.Structure):
         ("init_T_lo", ctypes.c_double), ("init_T_hi", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
         ("check_interval", ctypes.c_int32),
+        ("init_u", ctypes.c_double * 3),
     ]
 
 
@@ -102,9 +104,23 @@ _lib.lbm_status_string.argtypes = [ctypes.c_int]
 _lib.lbm_status_string.restype = ctypes.c_char_p
 _lib.lbm_last_error.argtypes = []
 _lib.lbm_last_error.restype = ctypes.c_char_p
+_lib.lbm_batch_create.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_V)]
+_lib.lbm_batch_destroy.argtypes = [_V]
+_lib.lbm_batch_add.argtypes = [_V, _V]
+_lib.lbm_batch_remove.argtypes = [_V, _V]
+_lib.lbm_batch_size.argtypes = [_V, ctypes.POINTER(ctypes.c_int32)]
+_lib.lbm_batch_member.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_V)]
+_lib.lbm_batch_step.argtypes = [_V, ctypes.c_int64]
+_lib.lbm_batch_residuals.argtypes = [_V, _D, _I64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+_lib.lbm_batch_set_launch.argtypes = [_V, ctypes.c_int32, ctypes.c_int32]
+_lib.lbm_batch_autotune.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]
+_lib.lbm_batch_set_graph.argtypes = [_V, ctypes.c_int32]
 for _name in ("lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_step",
               "lbm_time", "lbm_derived_params", "lbm_fields", "lbm_nusselt", "lbm_residual",
-              "lbm_totals", "lbm_get_state", "lbm_set_state"):
+              "lbm_totals", "lbm_get_state", "lbm_set_state", "lbm_batch_create", "lbm_batch_destroy",
+              "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size", "lbm_batch_member", "lbm_batch_step",
+              "lbm_batch_residuals", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_set_graph"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -134,9 +150,10 @@ def make_params(workload: dict, precision: str | int = "fp64", check_interval: i
                 p.face[k].T_wall = float(fc.get("T_wall", 0.0))
                 for a in range(3):
                     p.face[k].u_wall[a] = float(fc.get("u_wall", (0.0, 0.0, 0.0))[a])
-        elif key == "accel":
+        elif key in ("accel", "init_u"):
+            arr = getattr(p, key)
             for a in range(3):
-                p.accel[a] = float(val[a])
+                arr[a] = float(val[a])
         elif key == "precision":
             continue
         elif key in _SKIP_KEYS:
@@ -187,12 +204,21 @@ class Lattice:
                                ctypes.c_size_t(self.nbytes), ctypes.c_void_p(self.stream.cuda_stream),
                                ctypes.byref(h)))
         self._h = h
+        self.batch = None
 
     # -- lifetime
     def close(self):
         if getattr(self, "_h", None):
+            if self.batch is not None:
+                self.batch.remove(self)
             _check(_lib.lbm_destroy(self._h))
             self._h = None
+
+    def _settle(self):
+        """Outputs were written on this lattice's stream: make them safe to use
+        on the caller's current stream."""
+        if self.stream.cuda_stream != torch.cuda.current_stream(self.device).cuda_stream:
+            self.stream.synchronize()
 
     def __del__(self):
         try:
@@ -226,6 +252,7 @@ class Lattice:
         out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device)
                for k in ("rho", "ux", "uy", "uz", "T")}
         _check(_lib.lbm_fields(self._h, *(_ptr(out[k]) for k in ("rho", "ux", "uy", "uz", "T"))))
+        self._settle()
         return out
 
     def nusselt(self):
@@ -249,6 +276,7 @@ class Lattice:
         f = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
         g = torch.empty((7,) + self.shape, dtype=torch.float64, device=self.device)
         _check(_lib.lbm_get_state(self._h, _ptr(f), _ptr(g)))
+        self._settle()
         return f, g
 
     def set_state(self, f, g):
@@ -258,3 +286,84 @@ class Lattice:
         _check(_lib.lbm_set_state(self._h, _ptr(f), _ptr(g)))
         # keep the inputs alive until the copy kernel has run
         self.stream.synchronize()
+
+
+class Batch:
+    """Many lattices advanced by one launch per time step (lbm_batch_* of the C
+    ABI).  Members must share lattice type and precision; they move to the
+    batch's stream.  ``graph=True`` replays whole check intervals from a HIP
+    graph, which needs a stream of its own: one is created when none is given."""
+
+    def __init__(self, check_interval: int, stream: torch.cuda.Stream | None = None, graph: bool = False,
+                 block: int | None = None, per_cu: int = 0, device=None):
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        if stream is None:
+            stream = torch.cuda.Stream(self.device) if graph else torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.check_interval = int(check_interval)
+        h = ctypes.c_void_p()
+        _check(_lib.lbm_batch_create(ctypes.c_void_p(stream.cuda_stream), self.check_interval, ctypes.byref(h)))
+        self._h = h
+        self.members: list[Lattice] = []
+        if block is not None or per_cu:
+            self.set_launch(256 if block is None else block, per_cu)
+        if graph:
+            _check(_lib.lbm_batch_set_graph(self._h, 1))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.lbm_batch_destroy(self._h))
+            for m in self.members:
+                m.batch = None
+            self.members = []
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __len__(self) -> int:
+        return len(self.members)
+
+    def add(self, lat: Lattice):
+        _check(_lib.lbm_batch_add(self._h, lat._h))
+        lat.stream = self.stream
+        lat.batch = self
+        self.members.append(lat)
+
+    def remove(self, lat: Lattice):
+        _check(_lib.lbm_batch_remove(self._h, lat._h))
+        lat.batch = None
+        self.members.remove(lat)
+
+    def step(self, n: int = 1):
+        _check(_lib.lbm_batch_step(self._h, int(n)))
+
+    def set_launch(self, block: int, per_cu: int = 0):
+        """Threads per tile and resident blocks per compute unit (0: one block per tile)."""
+        _check(_lib.lbm_batch_set_launch(self._h, int(block), int(per_cu)))
+
+    def autotune(self, steps: int = 20):
+        """Times every launch shape over ``steps`` real steps; returns the
+        chosen (block, per_cu)."""
+        b = ctypes.c_int32()
+        c = ctypes.c_int32()
+        _check(_lib.lbm_batch_autotune(self._h, int(steps), ctypes.byref(b), ctypes.byref(c)))
+        return int(b.value), int(c.value)
+
+    def residuals(self):
+        """(r, at_step, unstable) lists in member order."""
+        n = len(self.members)
+        r = (ctypes.c_double * max(n, 1))()
+        at = (ctypes.c_int64 * max(n, 1))()
+        un = (ctypes.c_int32 * max(n, 1))()
+        _check(_lib.lbm_batch_residuals(self._h, r, at, un, n))
+        return [float(v) for v in r[:n]], [int(v) for v in at[:n]], [bool(v) for v in un[:n]]

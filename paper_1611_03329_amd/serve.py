@@ -1,0 +1,220 @@
+"""Steady-state solve serving on one GPU: continuous batching of lattice
+solves behind the batch entry points of the C ABI.
+
+A request is one porous-cavity (or channel) workload to be run until its
+residual r (the relative change of u and of theta over one step, checked every
+K steps on the GPU) falls below a tolerance.  The server
+
+  * admits arrived requests first come, first served, while their device bytes
+    (lbm_required_bytes) fit the HBM budget and a member slot is free;
+  * keeps every admitted state resident in device memory and steps all of
+    them together, one batch launch per time step, K steps per host
+    round-trip (replayed from a HIP graph when enabled);
+  * retires a member as soon as a check finds it converged (or unstable, or
+    past the step cap), reads its Nusselt numbers and frees its memory, which
+    lets the next waiting request in.
+
+Admission and retirement happen only between chunks of K steps, where the
+batch's step counter is a multiple of K; a new lattice (time 0) then joins with
+its checks on the same member times as when it runs alone, so every result -
+steps to converge, residual, Nusselt numbers, state - is bit for bit the same
+alone and in any mix.
+
+``solve_sequential`` is the baseline: the same requests one after another,
+each on its own lattice with lbm_step, in plain FP32 by default.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import deque
+
+import torch
+
+from .lbm import Batch, Lattice, make_params, required_bytes
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the run
+    workload: dict
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    name: str
+    nodes: int
+    arrival: float
+    admitted: float = math.nan
+    finished: float = math.nan
+    steps: int = 0          # time steps the lattice took
+    checked_at: int = -1    # member time of the last residual check
+    residual: float = -1.0
+    converged: bool = False
+    unstable: bool = False
+    nu: tuple = ()          # face Nusselt numbers at retirement
+
+    @property
+    def latency(self) -> float:
+        """Time to converge: arrival to retirement, queueing included."""
+        return self.finished - self.arrival
+
+
+def as_requests(stream) -> list:
+    """(arrival_seconds, workload) pairs -> Request list in arrival order."""
+    return [Request(i, float(t), wl) for i, (t, wl) in enumerate(sorted(stream, key=lambda p: p[0]))]
+
+
+def _done(res: Result, r: float, at: int, unstable: bool, steps: int, tol: float, max_steps: int) -> bool:
+    res.steps = steps
+    if at >= 0:
+        res.checked_at, res.residual = at, r
+    if unstable:
+        res.unstable = True
+        return True
+    if at > 0 and r < tol:
+        res.converged = True
+        return True
+    return steps >= max_steps
+
+
+class Server:
+    """Continuous-batching solve server on the current device."""
+
+    def __init__(self, precision: str = "fp16", check_interval: int = 100, tol: float = 1e-6,
+                 max_steps: int = 200_000, hbm_budget: int | None = None, max_members: int = 256,
+                 graph: bool = True, launch: tuple | None = None, device=None):
+        if check_interval <= 0 or check_interval % 2:
+            raise ValueError("check_interval must be a positive even number (chunks keep the parity)")
+        self.precision = precision
+        self.K = int(check_interval)
+        self.tol = float(tol)
+        self.max_steps = int(max_steps)
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            hbm_budget = int(0.8 * free)
+        self.hbm_budget = int(hbm_budget)
+        self.max_members = int(max_members)
+        self.batch = Batch(self.K, graph=graph, device=self.device)
+        if launch is not None:
+            self.batch.set_launch(*launch)
+        self.stats = {"chunks": 0, "lattice_steps": 0, "node_steps": 0, "peak_members": 0, "peak_bytes": 0}
+
+    def close(self):
+        self.batch.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def run(self, requests: list, clock=time.perf_counter) -> list:
+        """Serves `requests` (arrival times relative to the call) to completion;
+        returns one Result per request, in request order."""
+        pending = deque(sorted(requests, key=lambda q: q.arrival))
+        need = {q.rid: required_bytes(make_params(q.workload, self.precision, self.K)) for q in requests}
+        for q in requests:
+            if need[q.rid] > self.hbm_budget:
+                raise ValueError(f"request {q.rid} needs {need[q.rid]} B, more than the HBM budget")
+        waiting = deque()
+        active = {}   # id(lattice) -> (lattice, Result, bytes)
+        results = {}
+        used = 0
+        t0 = clock()
+        while pending or waiting or active:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admission, first come first served, between chunks
+            while waiting and len(active) < self.max_members and used + need[waiting[0].rid] <= self.hbm_budget:
+                q = waiting.popleft()
+                lat = Lattice(q.workload, self.precision, device=self.device)
+                self.batch.add(lat)
+                res = Result(q.rid, q.workload.get("name", ""), lat.nodes, q.arrival, admitted=clock() - t0)
+                active[id(lat)] = (lat, res, need[q.rid])
+                used += need[q.rid]
+            self.stats["peak_members"] = max(self.stats["peak_members"], len(active))
+            self.stats["peak_bytes"] = max(self.stats["peak_bytes"], used)
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, pending[0].arrival - (clock() - t0)))
+                continue
+            self.batch.step(self.K)
+            self.stats["chunks"] += 1
+            nodes = sum(v[0].nodes for v in active.values())
+            self.stats["lattice_steps"] += self.K * len(active)
+            self.stats["node_steps"] += self.K * nodes
+            r, at, un = self.batch.residuals()
+            for lat, rr, aa, uu in list(zip(list(self.batch.members), r, at, un)):
+                _, res, nb = active[id(lat)]
+                if _done(res, rr, aa, uu, lat.time, self.tol, self.max_steps):
+                    self.batch.remove(lat)
+                    if not res.unstable:
+                        res.nu = tuple(lat.nusselt())
+                    res.finished = clock() - t0
+                    lat.close()
+                    del active[id(lat)]
+                    used -= nb
+                    results[res.rid] = res
+        return [results[q.rid] for q in requests]
+
+
+def solve_sequential(requests: list, precision: str = "fp32", check_interval: int = 100, tol: float = 1e-6,
+                     max_steps: int = 200_000, clock=time.perf_counter, device=None) -> list:
+    """The baseline: each request alone on its own lattice (lbm_step), one after
+    another in arrival order, with the same check schedule and stopping rule."""
+    K = int(check_interval)
+    device = torch.device("cuda") if device is None else torch.device(device)
+    out = []
+    t0 = clock()
+    for q in sorted(requests, key=lambda q: q.arrival):
+        now = clock() - t0
+        if q.arrival > now:
+            time.sleep(q.arrival - now)
+        lat = Lattice(q.workload, precision, check_interval=K, device=device)
+        res = Result(q.rid, q.workload.get("name", ""), lat.nodes, q.arrival, admitted=clock() - t0)
+        while True:
+            lat.step(K)
+            lat.stream.synchronize()
+            try:
+                r, at = lat.residual()
+                un = False
+            except Exception as e:  # the residual check found the lattice unstable
+                if getattr(e, "status", None) != 4:
+                    raise
+                r, at, un = math.nan, lat.time - K, True
+            if _done(res, r, at, un, lat.time, tol, max_steps):
+                break
+        if not res.unstable:
+            res.nu = tuple(lat.nusselt())
+        res.finished = clock() - t0
+        lat.close()
+        out.append(res)
+    order = {q.rid: i for i, q in enumerate(requests)}
+    return sorted(out, key=lambda r: order[r.rid])
+
+
+def summarize(results: list) -> dict:
+    """p50/p99 time to converge, solves/s and aggregate MLUPS of one run."""
+    import numpy as np
+    fin = [r for r in results if not math.isnan(r.finished)]
+    lat = np.array([r.latency for r in fin])
+    span = max(r.finished for r in fin) - min(r.arrival for r in fin) if fin else math.nan
+    node_steps = sum(r.nodes * r.steps for r in fin)
+    return {
+        "requests": len(results),
+        "converged": sum(r.converged for r in results),
+        "unstable": sum(r.unstable for r in results),
+        "capped": sum((not r.converged) and (not r.unstable) for r in results),
+        "p50_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
+        "p99_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
+        "makespan_s": span,
+        "solves_per_s": len(fin) / span if span > 0 else math.nan,
+        "mlups": node_steps / span / 1e6 if span > 0 else math.nan,
+        "steps_total": int(sum(r.steps for r in fin)),
+    }

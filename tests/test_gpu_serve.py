@@ -1,0 +1,88 @@
+"""GPU tests of the serving loop: continuous batching of steady-state solves
+with HBM-budget admission and graph-replayed chunks.  Every result must be the
+same alone and in the mix (steps to converge, residual and Nusselt numbers bit
+for bit), and the same as the sequential baseline in the same precision."""
+import sys
+
+import pytest
+
+import lbm_inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1611_03329_amd import make_params, required_bytes  # noqa: E402
+from paper_1611_03329_amd.serve import Request, Server, solve_sequential, summarize  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _requests():
+    """Six small cavities of uneven sizes and parameters, arriving within 20 ms."""
+    draws = [((16, 16, 16), 0.4, 1e-2, 2e3), ((20, 18, 14), 0.7, 1e-3, 5e3), ((12, 12, 12), 0.9, 1e-1, 1e3),
+             ((24, 16, 20), 0.5, 1e-4, 1e4), ((14, 22, 18), 0.6, 5e-2, 3e3), ((18, 18, 18), 0.3, 1e-2, 8e3)]
+    out = []
+    for i, (shape, phi, da, ra) in enumerate(draws):
+        wl = lbm_inputs.cavity(shape, porosity=phi, darcy=da, rayleigh=ra, seed=40 + i)
+        wl["name"] = f"req{i}"
+        out.append(Request(i, 0.004 * i, wl))
+    return out
+
+
+KW = dict(check_interval=100, tol=1e-6, max_steps=30000)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_results_are_the_same_alone_and_in_the_mix(prec):
+    reqs = _requests()
+    _say(f"case serve mix vs alone {prec}: {len(reqs)} requests")
+    with Server(prec, graph=True, **KW) as srv:
+        mix = srv.run(reqs)
+        assert srv.stats["peak_members"] >= 2
+    for q, m in zip(reqs, mix):
+        assert m.converged, (q.rid, m.residual, m.steps)
+        with Server(prec, graph=True, **KW) as srv1:
+            (a,) = srv1.run([Request(q.rid, 0.0, q.workload)])
+        assert (a.steps, a.checked_at, a.residual, a.nu) == (m.steps, m.checked_at, m.residual, m.nu), q.rid
+    s = summarize(mix)
+    _say(f"{prec}: {s}")
+    assert s["converged"] == len(reqs)
+
+
+def test_served_fp32_equals_sequential_fp32():
+    """Same precision: the served and the sequential solve take the same number
+    of steps and give the same Nusselt numbers (the states are identical; the
+    residuals differ at most by summation order)."""
+    reqs = _requests()
+    _say("case serve vs sequential fp32")
+    with Server("fp32", graph=False, **KW) as srv:
+        mix = srv.run(reqs)
+    seq = solve_sequential(reqs, "fp32", **KW)
+    for m, s in zip(mix, seq):
+        assert m.converged and s.converged
+        assert m.steps == s.steps and m.checked_at == s.checked_at, (m.rid, m.steps, s.steps)
+        assert m.nu == s.nu
+        assert abs(m.residual - s.residual) <= 1e-9 * s.residual
+
+
+def test_admission_respects_the_hbm_budget():
+    """With room for about two of the requests at a time the server never holds
+    more than the budget, and still completes every request."""
+    reqs = _requests()
+    need = sorted(required_bytes(make_params(q.workload, "fp16", 100)) for q in reqs)
+    budget = need[-1] + need[-2]
+    _say(f"case admission budget {budget} B")
+    with Server("fp16", hbm_budget=budget, **KW) as srv:
+        res = srv.run(reqs)
+        assert srv.stats["peak_bytes"] <= budget
+        assert srv.stats["peak_members"] <= 3
+    assert all(r.converged for r in res)
+    # first come, first served: admission times follow arrival order
+    adm = [r.admitted for r in sorted(res, key=lambda r: r.arrival)]
+    assert adm == sorted(adm)
