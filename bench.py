@@ -1,6 +1,6 @@
 """Benchmark of the fused DDF-MRT porous-convection step on one MI355X.
 
-Workload: the 256^3 porous cavity (D3Q19 flow + D3Q7 temperature, FP32
+Default workload: the 256^3 porous cavity (D3Q19 flow + D3Q7 temperature, FP32
 storage and arithmetic, phi 0.4, Da 1e-4, Ra 1e6, Pr 1, seed 2), residual
 checks every 100 steps as part of the step.  A "step" is one lattice
 Boltzmann time step of the whole box.  The state is resident in HBM before
@@ -9,6 +9,12 @@ the timed region starts.
 Prints ONE JSON line: MLUPS (whole job), the roofline of the step kernel
 (algorithmic bytes = 2 x 26 populations x 4 B = 208 B per node per step) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+--workload batched | served runs the solve benchmarks instead (one JSON line
+each): 64 cavities of uneven sizes and parameters solved to residual 1e-6 in
+one batch (all arriving at once), or a Poisson stream of cavity solve requests
+served with continuous batching under an HBM budget; both against the same
+solves run one after another in plain FP32.
 """
 from __future__ import annotations
 
@@ -67,9 +73,94 @@ def cpu_baseline(workload: dict, steps: int) -> dict:
     }
 
 
+def _say(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def tune_launch(workloads, precision: str, interval: int, span: bool):
+    """Launch shape for a batch of these workloads, chosen by the batch
+    autotuner on throw-away copies (the timed solves start fresh)."""
+    from paper_1611_03329_amd import Batch, Lattice
+    b = Batch(interval, span=span)
+    lats = [Lattice(w, precision) for w in workloads]
+    for lat in lats:
+        b.add(lat)
+    shape = b.autotune()
+    b.close()
+    for lat in lats:
+        lat.close()
+    return shape
+
+
+def bench_solves(args, kind: str) -> int:
+    """Solves to residual 1e-6: served (continuous batching, FP16 storage with
+    the FP32 finish) against one-after-another plain FP32 solves."""
+    import torch
+
+    import lbm_inputs
+    from paper_1611_03329_amd.serve import Request, Server, as_requests, solve_sequential, summarize
+
+    torch.cuda.set_device(0)
+    if kind == "batched":
+        reqs = [Request(i, 0.0, w) for i, w in enumerate(lbm_inputs.config_batch(args.count))]
+        budget = None
+        workload = (f"{len(reqs)} porous cavities, edge from {{32,48,64,96,128}}, phi U[0.3,0.9], Da logU[1e-5,1e-1], "
+                    "Ra logU[1e3,1e6], Pr 1, seed 4, all submitted at t=0")
+        metric = "batched-solve throughput (solves to residual 1e-6)"
+    else:
+        reqs = as_requests(lbm_inputs.config_serving(args.count, rate=args.rate))
+        budget = int(args.hbm_budget_gib * (1 << 30))
+        workload = (f"Poisson stream of {len(reqs)} porous-cavity solve requests at {args.rate} req/s, edge logU[48,192], "
+                    f"parameters as the batched config, seed 5, HBM budget {args.hbm_budget_gib} GiB")
+        metric = "served-solve throughput and p50/p99 time-to-converge (residual 1e-6)"
+    nodes = sum(q.workload["nx"] * q.workload["ny"] * q.workload["nz"] for q in reqs)
+    _say(f"{kind}: {len(reqs)} requests, {nodes} nodes in all; tuning the launch shape")
+    shape = tune_launch([q.workload for q in reqs[:args.tune_count]], "fp16", args.fp16_interval, True)
+    _say(f"launch shape (threads, blocks/CU, group bytes) = {shape}")
+    with Server("fp16", check_interval=100, tol=1e-6, max_steps=args.max_steps, hbm_budget=budget,
+                launch=shape, fp16_interval=args.fp16_interval) as srv:
+        served = srv.run(reqs, progress=_say)
+        stats = dict(srv.stats)
+    s_sum = summarize(served)
+    _say(f"served: {s_sum}")
+    seq = solve_sequential(reqs, "fp32", check_interval=100, tol=1e-6, max_steps=args.max_steps, progress=_say)
+    q_sum = summarize(seq)
+    _say(f"sequential fp32: {q_sum}")
+    dnu = [abs(a.nu[0] - b.nu[0]) / abs(b.nu[0]) for a, b in zip(served, seq) if a.nu and b.nu]
+    line = {
+        "metric": metric,
+        "value": round(s_sum["solves_per_s"], 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16 storage then f32 (f32 arithmetic)",
+        "data": "synthetic",
+        "config": {"workload": workload, "requests": len(reqs), "nodes": nodes, "check_interval": 100,
+                   "fp16_interval": args.fp16_interval, "max_steps": args.max_steps, "launch": list(shape),
+                   "parallelism": "single GPU"},
+        "served": {**s_sum, "promoted": stats["promoted"], "peak_members": stats["peak_members"],
+                   "peak_bytes": stats["peak_bytes"]},
+        "sequential_fp32": q_sum,
+        "speedup_solves_per_s": round(s_sum["solves_per_s"] / q_sum["solves_per_s"], 3),
+        "nu_hot_rel_diff_vs_sequential": {"max": max(dnu) if dnu else None,
+                                          "median": sorted(dnu)[len(dnu) // 2] if dnu else None},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("cavity256", "batched", "served"), default="cavity256")
+    ap.add_argument("--count", type=int, default=64, help="solves in the batched / served workloads")
+    ap.add_argument("--rate", type=float, default=20.0, help="served: mean arrivals per second")
+    ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="served: HBM budget for admission")
+    ap.add_argument("--max-steps", type=int, default=100_000, help="solves: step cap per solve")
+    ap.add_argument("--fp16-interval", type=int, default=500, help="solves: FP16 residual interval")
+    ap.add_argument("--tune-count", type=int, default=16, help="solves: workloads used to tune the launch shape")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--check-interval", type=int, default=100)
@@ -84,6 +175,8 @@ def main(argv=None) -> int:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         return 2
+    if args.workload != "cavity256":
+        return bench_solves(args, args.workload)
 
     import torch
 

@@ -206,10 +206,19 @@ lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g);
  * counter is kept; the pending residual snapshot is discarded.  Asynchronous. */
 lbm_status lbm_set_state(lbm_lattice* h, const double* f, const double* g);
 
+/* Copies the current pre-collision state of src into dst, converting the
+ * storage precision (e.g. an FP16-storage lattice into an FP32 one).  Both must
+ * have the same lattice type, shape and rest state (varpi, sigma, T_ref); the
+ * physical parameters may differ.  dst keeps its time counter; its pending
+ * residual snapshot is discarded; dst must not be in a batch.  Waits for src's
+ * stream if it differs from dst's, then enqueues on dst's stream. */
+lbm_status lbm_transfer_state(lbm_lattice* dst, lbm_lattice* src);
+
 /* ---------------------------------------------------------------- batches
  * A batch advances many independent lattices (members) by the same fused time
- * step of lbm_step, with one kernel launch per step for all members (two when
- * some members have moving walls or open faces and others not).  A member's
+ * step of lbm_step, one kernel launch per step for a whole group of members
+ * (groups: see lbm_batch_set_launch; by default one group, or two when some
+ * members have moving walls or open faces and others not).  A member's
  * state after any number of steps is bit for bit the one lbm_step gives it,
  * and its residuals depend on nothing else in the batch (they are summed in a
  * fixed order set by the member's size and the block size alone).
@@ -259,20 +268,32 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
  * unstable.  Synchronizes. */
 lbm_status lbm_batch_residuals(lbm_batch* b, double* r, int64_t* at_step, int32_t* unstable, int32_t count);
 
-/* Launch shape of the batch kernel: `block` threads per tile (64, 128 or 256;
- * default 256) and, if blocks_per_cu > 0, a persistent grid of blocks_per_cu
- * blocks per compute unit (at most the tile count) whose blocks walk the tile
- * list; 0 (default) launches one block per tile.  Results do not depend on the
- * launch shape except through the residual's summation order, which follows
- * `block`. */
-lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu);
+/* Launch shape: `block` threads per tile (64, 128 or 256; default 256); if
+ * blocks_per_cu > 0 a persistent grid of blocks_per_cu blocks per compute unit
+ * (at most the tile count) whose blocks walk the tile list, else (default) one
+ * block per tile; and the group size limit group_bytes (0, the default: one
+ * group per wall-rule set).  Whole check intervals run group by group, so a
+ * group whose populations fit the last-level cache is streamed from there.
+ * Results do not depend on the launch shape except through the residual's
+ * summation order, which follows `block`. */
+lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu, uint64_t group_bytes);
 
-/* Runs 1 + steps batch steps at each launch shape (block in {64, 128, 256} x
- * blocks_per_cu in {0, 4, 8, 16}), times the last `steps` with HIP events (graph
- * replay off meanwhile) and keeps the fastest; writes it to *block and
- * *blocks_per_cu where non-NULL.  The steps advance the members.
- * Synchronizes. */
-lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* block, int32_t* blocks_per_cu);
+/* Chooses the launch shape by timing whole check intervals (HIP events, graph
+ * replay off meanwhile): first group_bytes in {0, 32, 64, 128, 256, 512} MiB, then
+ * block in {64, 128, 256}, then blocks_per_cu in {0, 4, 8}; each candidate
+ * runs one untimed and one timed interval, after the batch first steps to the
+ * start of an interval.  Writes the choice where the pointers are non-NULL and
+ * keeps it.  The steps advance the members.  Synchronizes. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t* block, int32_t* blocks_per_cu, uint64_t* group_bytes);
+
+/* on != 0: the residual of a check compares with the state of K steps before
+ * (r = max(|u(n) - u(n-K)|_2 / |u(n)|_2, |theta(n) - theta(n-K)|_2 /
+ * |theta(n)|_2)) instead of one step before; one step per interval then both
+ * compares and snapshots (steps s % K == 0).  The change over K steps stands
+ * out from rounding noise of the stored populations (FP16 storage) K times
+ * better than the one-step change.  Only at the start of a check interval;
+ * every member's next check is then its first. */
+lbm_status lbm_batch_set_span(lbm_batch* b, int32_t on);
 
 /* on != 0: whole check intervals (the K steps from a batch step s with
  * s % K == 0) are recorded once into a HIP graph and replayed; the graph is

@@ -59,6 +59,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_step_batch(const Member<S, C>* __
       else step_block<Lat, S, C, ODD, kModePlain, GEN>(kp, sto, snap, part, lb);
       // the block reduction's shared slots are reused by the next tile
       __syncthreads();
+    } else if constexpr (MODE == kModeSpan) {
+      // without a snapshot yet the member only takes one
+      if (mem[m].check) step_block<Lat, S, C, ODD, kModeSpan, GEN>(kp, sto, snap, part, lb);
+      else step_block<Lat, S, C, ODD, kModeSnapshot, GEN>(kp, sto, snap, part, lb);
+      __syncthreads();
     } else {
       step_block<Lat, S, C, ODD, MODE, GEN>(kp, sto, snap, part, lb);
     }

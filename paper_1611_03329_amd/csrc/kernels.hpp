@@ -393,13 +393,14 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], unsigned maxmask) 
 }
 
 // ------------------------------------------------------------------ step
-enum : int { kModePlain = 0, kModeSnapshot = 1, kModeCompare = 2 };
+enum : int { kModePlain = 0, kModeSnapshot = 1, kModeCompare = 2, kModeSpan = 3 };
 constexpr int kPartStride = 8;  // doubles per block in the partials buffer
 
 // One fused time step of the nodes of one block (block index lb of the lattice).
 //   MODE 1 also stores u and T of the pre-collision state into snap (4 planes of n);
 //   MODE 2 also accumulates, per block, sum|u - u_snap|^2, sum|u|^2,
-//   sum (theta - theta_snap)^2, sum theta^2 and max|u| into part[lb].
+//   sum (theta - theta_snap)^2, sum theta^2 and max|u| into part[lb];
+//   MODE 3 does both: it compares with the snapshot, then replaces it.
 template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
 __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state, C* __restrict__ snap,
                                            double* __restrict__ part, int lb) {
@@ -413,13 +414,7 @@ __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state,
     gather<Lat, ODD, GEN, S, C>(kp, state, n, nb, h, p);
     const Macro<C> M = macro<Lat, C>(kp, h, p);
     LBM_GLOBAL C* sn = gbl(snap);
-    if constexpr (MODE == kModeSnapshot) {
-      sn[n] = M.ux;
-      sn[n + kp.n] = M.uy;
-      sn[n + 2 * kp.n] = M.uz;
-      sn[n + 3 * kp.n] = M.T;
-    }
-    if constexpr (MODE == kModeCompare) {
+    if constexpr (MODE == kModeCompare || MODE == kModeSpan) {
       const double ux = M.ux, uy = M.uy, uz = M.uz, T = M.T;
       const double dx = ux - (double)sn[n], dy = uy - (double)sn[n + kp.n], dz = uz - (double)sn[n + 2 * kp.n];
       const double dT = (T - (double)sn[n + 3 * kp.n]) * (double)kp.inv_dT;
@@ -431,11 +426,17 @@ __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state,
       red[3] = th * th;
       red[4] = sqrt(uu);
     }
+    if constexpr (MODE == kModeSnapshot || MODE == kModeSpan) {
+      sn[n] = M.ux;
+      sn[n + kp.n] = M.uy;
+      sn[n + 2 * kp.n] = M.uz;
+      sn[n + 3 * kp.n] = M.T;
+    }
     collide_flow<Lat, C>(kp, M, h);
     collide_heat<C>(kp, M, p);
     scatter<Lat, ODD, GEN, S, C>(kp, state, n, nb, h, p, M);
   }
-  if constexpr (MODE == kModeCompare) {
+  if constexpr (MODE == kModeCompare || MODE == kModeSpan) {
     block_reduce<5>(red, 1u << 4);
     if (threadIdx.x == 0) {
       LBM_GLOBAL double* pt = gbl(part);
@@ -705,6 +706,31 @@ __global__ void __launch_bounds__(kMaxBlock) k_set_state(const KParams<C> kp, co
     if (k == 0) st_rs<S, C>(state, ps + (uint32_t)n, v);
     else st_mg<S, C>(state, gplane<Lat>(k) * ps + (uint32_t)n, v);
   }
+}
+
+// Copies the pre-collision state of lattice `src` (at parity ODD) into lattice
+// `dst` of the same shape and rest state, converting between storage types;
+// dst is written in the even-parity layout.  Both store departures from the
+// same rest state, so the copy is a plain conversion of each stored value.
+template <class Lat, class SS, class CS, bool ODD, class SD, class CD>
+__global__ void __launch_bounds__(kMaxBlock) k_transfer(const KParams<CS> kps, const SS src, const KParams<CD> kpd,
+                                                        const SD dst) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= kps.n) return;
+  int x, y, z;
+  node_coords(kps, n, x, y, z);
+  const Nbr nb = make_nbr(kps, x, y, z);
+  CS h[Lat::Q], p[7];
+  gather<Lat, ODD, true, SS, CS>(kps, src, n, nb, h, p);
+  const uint32_t ps = (uint32_t)kpd.pstride;
+  static_for<0, Lat::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    if constexpr (i == 0) st_rs<SD, CD>(dst, (uint32_t)n, (CD)h[0]);
+    else st_mf<SD, CD>(dst, fplane<Lat>(i) * ps + (uint32_t)n, (CD)h[i]);
+  });
+  st_rs<SD, CD>(dst, ps + (uint32_t)n, (CD)p[0]);
+#pragma unroll
+  for (int k = 1; k < 7; ++k) st_mg<SD, CD>(dst, gplane<Lat>(k) * ps + (uint32_t)n, (CD)p[k]);
 }
 
 }  // namespace lbm

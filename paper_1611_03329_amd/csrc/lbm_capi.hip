@@ -676,59 +676,109 @@ extern "C" lbm_status lbm_set_state(lbm_lattice* h, const double* f, const doubl
   return LBM_OK;
 }
 
+extern "C" lbm_status lbm_transfer_state(lbm_lattice* dst, lbm_lattice* src) {
+  if (!dst || !src) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (dst == src) return fail(LBM_ERR_INVALID_ARG, "source and destination are the same lattice");
+  if (dst->batch) return fail(LBM_ERR_INVALID_ARG, "the destination is in a batch: remove it first");
+  if (dst->q != src->q || dst->p.nx != src->p.nx || dst->p.ny != src->p.ny || dst->p.nz != src->p.nz)
+    return fail(LBM_ERR_INVALID_ARG, "source and destination differ in lattice type or shape");
+  if (dst->p.varpi != src->p.varpi || dst->p.sigma != src->p.sigma || dst->p.T_ref != src->p.T_ref)
+    return fail(LBM_ERR_INVALID_ARG, "source and destination differ in their rest state (varpi, sigma, T_ref)");
+  // the source's pending work (on its own stream) comes first
+  if (src->stream != dst->stream) HIP_TRY(hipStreamSynchronize(src->stream));
+  with_types(src, [&](auto lat_s, auto ss_t, auto cs_t, const auto& kps) {
+    with_types(dst, [&](auto lat_d, auto sd_t, auto cd_t, const auto& kpd) {
+      using Lat = decltype(lat_s);
+      if constexpr (std::is_same_v<Lat, decltype(lat_d)>) {
+        using SS = decltype(ss_t);
+        using CS = decltype(cs_t);
+        using SD = decltype(sd_t);
+        using CD = decltype(cd_t);
+        if (src->parity)
+          hipLaunchKernelGGL((k_transfer<Lat, SS, CS, true, SD, CD>), dim3(dst->nblocks), dim3(dst->block), 0,
+                             dst->stream, kps, make_store<SS>(src), kpd, make_store<SD>(dst));
+        else
+          hipLaunchKernelGGL((k_transfer<Lat, SS, CS, false, SD, CD>), dim3(dst->nblocks), dim3(dst->block), 0,
+                             dst->stream, kps, make_store<SS>(src), kpd, make_store<SD>(dst));
+      }
+    });
+  });
+  lbm_status ls = launch_check("transfer_state");
+  if (ls != LBM_OK) return ls;
+  dst->parity = 0;
+  dst->snapshot_valid = false;
+  return LBM_OK;
+}
+
 // ------------------------------------------------------------------ batches
-// A batch advances its member lattices together, one launch per time step (two
-// when members need both the lean and the general wall rules).  Members share
-// the lattice type, precision, stream and time parity.  The residual check runs
-// on the batch's own schedule: batch step s snapshots when (s + 1) % K == 0 and
-// compares when s % K == 0, s > 0; a member compares only once it has taken a
-// snapshot inside the batch.
+// A batch advances its member lattices together.  Members share the lattice
+// type, precision, stream and time parity.  They are packed, in join order,
+// into launch groups: members with the lean wall rules and members with the
+// general ones never share a group, and with a group size limit G > 0 a group
+// holds members whose states add up to at most G bytes (one larger member
+// forms a group of its own).  One kernel launch advances one group by one step.
+//
+// Whole check intervals (K steps from a batch step s with s % K == 0) run group
+// by group: all K steps of the first group, then of the next, so that a group
+// whose state fits the device's last-level cache is streamed from there rather
+// than from HBM.  Other steps run all groups step by step.  Members are
+// independent, so the order changes no result.
+//
+// The residual check follows the batch's step counter s.  By default step s
+// snapshots when (s + 1) % K == 0 and compares when s % K == 0, s > 0: r is the
+// change over one step.  With the span residual, step s with s % K == 0
+// compares with the snapshot of K steps before and takes a new one: r is the
+// change over the whole check interval.  A member compares only once it has
+// taken a snapshot inside the batch.
 struct lbm_batch {
   hipStream_t stream = nullptr;
   int q = 0, prec = -1;
   int check = 0;
-  int block = 256;     // threads per tile
-  int per_cu = 0;      // resident blocks per compute unit (persistent launch); 0: one block per tile
-  int ncu = 0;         // compute units of the device
+  int block = 256;           // threads per tile
+  int per_cu = 0;            // resident blocks per compute unit (persistent launch); 0: one block per tile
+  int ncu = 0;               // compute units of the device
+  uint64_t group_bytes = 0;  // group size limit; 0: one group per wall-rule set
   int64_t s = 0;
   int parity = 0;
   bool use_graph = false;
+  bool span = false;  // residual over the check interval instead of one step
   std::vector<lbm_lattice*> members;  // join order
   std::vector<int> compare_ok;        // the member holds a snapshot for the next compare
   std::vector<int64_t> last_check;    // lattice time of the member's last compare
   std::vector<int> fresh;             // a result row not yet pulled into the member
-  // device descriptors, per group (0: lean rules, 1: general rules)
-  void* dev_mem[2] = {nullptr, nullptr};
-  size_t dev_cap[2] = {0, 0};
-  int count[2] = {0, 0};
-  int blocks[2] = {0, 0};
-  std::vector<int> slot;  // member index -> row of out (group 0 rows first)
+  struct Group {
+    int gen, first, count, tiles;
+  };
+  std::vector<Group> groups;
+  std::vector<int> slot;  // member index -> its row in the member table and in out
+  void* dev_mem = nullptr;
+  size_t dev_cap = 0;
   double* dev_out = nullptr;
   double* host_out = nullptr;
   size_t out_cap = 0;
   void* staging = nullptr;  // pinned upload buffer
   size_t staging_cap = 0;
-  hipEvent_t staged = nullptr;
   bool dirty = true;
-  // a captured chunk of K steps starting at a compare step, per start parity
+  // a captured check interval, per start parity, and what its launches depend
+  // on besides the member table's contents
   hipGraphExec_t graph[2] = {nullptr, nullptr};
-  // what the captured launches depend on besides the descriptors' contents
-  struct Key {
-    const void* mem[2];
-    int count[2], tiles[2], block, grid[2];
-    const double* out;
-    const double* host;
-    bool operator==(const Key& o) const { return std::memcmp(this, &o, sizeof(Key)) == 0; }
-  } key{};
+  std::vector<int64_t> key;
 };
-
-static int batch_grid(const lbm_batch* b, int grp) {
-  const int tiles = b->blocks[grp];
-  return b->per_cu > 0 ? std::min(tiles, b->per_cu * std::max(b->ncu, 1)) : tiles;
-}
 
 static bool member_general(const lbm_lattice* h) {
   return h->kd.moving || h->kd.open_flow || h->kd.open_heat;
+}
+
+// Bytes of populations a step streams for member h.
+static uint64_t member_state_bytes(const lbm_lattice* h) {
+  const uint64_t ps = (uint64_t)h->pstride;
+  if (h->prec == LBM_FP64) return ps * 8u * (uint64_t)(h->q + 7);
+  if (h->prec == LBM_FP32) return ps * 4u * (uint64_t)(h->q + 7);
+  return ps * (2u * (uint64_t)(h->q - 1) + 4u * 8u);
+}
+
+static int batch_grid(const lbm_batch* b, int tiles) {
+  return b->per_cu > 0 ? std::min(tiles, b->per_cu * std::max(b->ncu, 1)) : tiles;
 }
 
 static void batch_drop_graphs(lbm_batch* b) {
@@ -740,7 +790,7 @@ static void batch_drop_graphs(lbm_batch* b) {
 }
 
 // Waits for the batch's stream and moves every new result row into its member's
-// own host mirror (the rows are laid out by the current descriptors).
+// own host mirror (the rows are laid out by the current member table).
 static lbm_status batch_pull(lbm_batch* b) {
   HIP_TRY(hipStreamSynchronize(b->stream));
   for (size_t i = 0; i < b->members.size(); ++i) {
@@ -756,38 +806,47 @@ static lbm_status batch_pull(lbm_batch* b) {
 static const KParams<double>& kp_of(const lbm_lattice* h, double) { return h->kd; }
 static const KParams<float>& kp_of(const lbm_lattice* h, float) { return h->kf; }
 
-template <class S, class C>
-static void fill_members(const lbm_batch* b, int grp, std::vector<Member<S, C>>& out) {
-  out.clear();
-  int block0 = 0;
-  for (size_t i = 0; i < b->members.size(); ++i) {
-    lbm_lattice* h = b->members[i];
-    if ((int)member_general(h) != grp) continue;
-    Member<S, C> m;
-    std::memset(&m, 0, sizeof(m));
-    m.kp = kp_of(h, C{});
-    m.sto = make_store<S>(h);
-    m.snap = static_cast<C*>(h->snap);
-    m.part = h->part;
-    m.res = h->res;
-    m.block0 = block0;
-    m.nblocks = (h->nodes + b->block - 1) / b->block;
-    m.check = b->compare_ok[i];
-    block0 += m.nblocks;
-    out.push_back(m);
-  }
-}
-
-// Rebuilds both descriptor groups and uploads them (stream-ordered copies from
-// pinned staging).  Pending result rows are pulled first: the rows move.
+// Rebuilds the groups and the member table and uploads the table (a
+// stream-ordered copy from pinned staging).  Pending result rows are pulled
+// first: the rows move.
 template <class S, class C>
 static lbm_status batch_upload_typed(lbm_batch* b) {
   lbm_status st_ = batch_pull(b);
   if (st_ != LBM_OK) return st_;
-  std::vector<Member<S, C>> g[2];
-  fill_members<S, C>(b, 0, g[0]);
-  fill_members<S, C>(b, 1, g[1]);
-  const size_t need = (g[0].size() + g[1].size()) * sizeof(Member<S, C>);
+  std::vector<Member<S, C>> table;
+  b->groups.clear();
+  b->slot.assign(b->members.size(), 0);
+  for (int gen = 0; gen < 2; ++gen) {
+    lbm_batch::Group cur{gen, (int)table.size(), 0, 0};
+    uint64_t bytes = 0;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+      lbm_lattice* h = b->members[i];
+      if ((int)member_general(h) != gen) continue;
+      const uint64_t mb = member_state_bytes(h);
+      if (cur.count > 0 && b->group_bytes > 0 && bytes + mb > b->group_bytes) {
+        b->groups.push_back(cur);
+        cur = lbm_batch::Group{gen, (int)table.size(), 0, 0};
+        bytes = 0;
+      }
+      Member<S, C> m;
+      std::memset(&m, 0, sizeof(m));
+      m.kp = kp_of(h, C{});
+      m.sto = make_store<S>(h);
+      m.snap = static_cast<C*>(h->snap);
+      m.part = h->part;
+      m.res = h->res;
+      m.block0 = cur.tiles;
+      m.nblocks = (h->nodes + b->block - 1) / b->block;
+      m.check = b->compare_ok[i];
+      cur.tiles += m.nblocks;
+      cur.count += 1;
+      bytes += mb;
+      b->slot[i] = (int)table.size();
+      table.push_back(m);
+    }
+    if (cur.count > 0) b->groups.push_back(cur);
+  }
+  const size_t need = table.size() * sizeof(Member<S, C>);
   if (need > b->staging_cap) {
     if (b->staging) (void)hipHostFree(b->staging);
     b->staging = nullptr;
@@ -795,31 +854,18 @@ static lbm_status batch_upload_typed(lbm_batch* b) {
     HIP_TRY(hipHostMalloc(&b->staging, need, hipHostMallocDefault));
     b->staging_cap = need;
   }
-  char* stage = static_cast<char*>(b->staging);
-  size_t off = 0;
-  b->slot.assign(b->members.size(), 0);
-  int row = 0;
-  for (int grp = 0; grp < 2; ++grp) {
-    const size_t bytes = g[grp].size() * sizeof(Member<S, C>);
-    if (bytes > b->dev_cap[grp]) {
-      if (b->dev_mem[grp]) (void)hipFree(b->dev_mem[grp]);
-      b->dev_mem[grp] = nullptr;
-      b->dev_cap[grp] = 0;
-      HIP_TRY(hipMalloc(&b->dev_mem[grp], bytes));
-      b->dev_cap[grp] = bytes;
-    }
-    if (bytes) {
-      std::memcpy(stage + off, g[grp].data(), bytes);
-      HIP_TRY(hipMemcpyAsync(b->dev_mem[grp], stage + off, bytes, hipMemcpyHostToDevice, b->stream));
-    }
-    off += bytes;
-    b->count[grp] = (int)g[grp].size();
-    b->blocks[grp] = g[grp].empty() ? 0 : g[grp].back().block0 + g[grp].back().nblocks;
-    for (size_t i = 0, k = 0; i < b->members.size(); ++i)
-      if ((int)member_general(b->members[i]) == grp) b->slot[i] = row + (int)(k++);
-    row += (int)g[grp].size();
+  if (need > b->dev_cap) {
+    if (b->dev_mem) (void)hipFree(b->dev_mem);
+    b->dev_mem = nullptr;
+    b->dev_cap = 0;
+    HIP_TRY(hipMalloc(&b->dev_mem, need));
+    b->dev_cap = need;
   }
-  const size_t out_need = (size_t)std::max(row, 1) * kPartStride * sizeof(double);
+  if (need) {
+    std::memcpy(b->staging, table.data(), need);
+    HIP_TRY(hipMemcpyAsync(b->dev_mem, b->staging, need, hipMemcpyHostToDevice, b->stream));
+  }
+  const size_t out_need = std::max<size_t>(table.size(), 1) * kPartStride * sizeof(double);
   if (out_need > b->out_cap) {
     if (b->dev_out) (void)hipFree(b->dev_out);
     if (b->host_out) (void)hipHostFree(b->host_out);
@@ -834,20 +880,12 @@ static lbm_status batch_upload_typed(lbm_batch* b) {
   // the staging buffer is rewritten by the next upload only after this one landed
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->dirty = false;
-  // captured launches read the descriptors from device memory: they stay valid
-  // while the buffers, the member counts and the launch shapes are unchanged
-  lbm_batch::Key k;
-  std::memset(&k, 0, sizeof(k));
-  for (int grp = 0; grp < 2; ++grp) {
-    k.mem[grp] = b->dev_mem[grp];
-    k.count[grp] = b->count[grp];
-    k.tiles[grp] = b->blocks[grp];
-    k.grid[grp] = batch_grid(b, grp);
-  }
-  k.block = b->block;
-  k.out = b->dev_out;
-  k.host = b->host_out;
-  if (!(k == b->key)) batch_drop_graphs(b);
+  // captured launches read the member table from device memory: they stay
+  // valid while the buffers, the groups and the launch shape are unchanged
+  std::vector<int64_t> k = {(int64_t)(uintptr_t)b->dev_mem, (int64_t)(uintptr_t)b->dev_out,
+                            (int64_t)(uintptr_t)b->host_out, b->block, b->per_cu, b->check};
+  for (const auto& g : b->groups) k.insert(k.end(), {g.gen, g.first, g.count, g.tiles});
+  if (k != b->key) batch_drop_graphs(b);
   b->key = k;
   return LBM_OK;
 }
@@ -870,68 +908,80 @@ static void batch_types(const lbm_batch* b, F&& f) {
 
 static lbm_status batch_upload(lbm_batch* b) {
   lbm_status st_ = LBM_OK;
-  batch_types(b, [&](auto, auto s_t, auto c_t) {
-    st_ = batch_upload_typed<decltype(s_t), decltype(c_t)>(b);
-  });
+  batch_types(b, [&](auto, auto s_t, auto c_t) { st_ = batch_upload_typed<decltype(s_t), decltype(c_t)>(b); });
   return st_;
-}
-
-template <class Lat, class S, class C, bool ODD, int MODE>
-static void batch_launch_mode(lbm_batch* b) {
-  for (int grp = 0; grp < 2; ++grp) {
-    if (!b->count[grp]) continue;
-    const auto* mem = static_cast<const Member<S, C>*>(b->dev_mem[grp]);
-    const int grid = batch_grid(b, grp);
-    if (grp == 0)
-      hipLaunchKernelGGL((k_step_batch<Lat, S, C, ODD, MODE, false>), dim3(grid), dim3(b->block), 0, b->stream,
-                         mem, b->count[grp], b->blocks[grp]);
-    else
-      hipLaunchKernelGGL((k_step_batch<Lat, S, C, ODD, MODE, true>), dim3(grid), dim3(b->block), 0, b->stream,
-                         mem, b->count[grp], b->blocks[grp]);
-  }
 }
 
 static int batch_mode(const lbm_batch* b, int64_t s) {
   const int64_t K = b->check;
-  if (K > 0 && (s + 1) % K == 0) return kModeSnapshot;
-  if (K > 0 && s > 0 && s % K == 0) return kModeCompare;
+  if (K <= 0) return kModePlain;
+  if (b->span) return s % K == 0 ? (s > 0 ? kModeSpan : kModeSnapshot) : kModePlain;
+  if ((s + 1) % K == 0) return kModeSnapshot;
+  if (s > 0 && s % K == 0) return kModeCompare;
   return kModePlain;
 }
 
-// Enqueues batch step s with the given parity and, after a compare step, the
-// per-member folds and one copy of all result rows to the host.
-static lbm_status batch_enqueue_step(lbm_batch* b, int64_t s, int parity) {
-  const int mode = batch_mode(b, s);
-  lbm_status st_ = LBM_OK;
+template <class Lat, class S, class C, bool ODD, int MODE>
+static void batch_launch_mode(const lbm_batch* b, const lbm_batch::Group& g) {
+  const auto* mem = static_cast<const Member<S, C>*>(b->dev_mem) + g.first;
+  const int grid = batch_grid(b, g.tiles);
+  if (g.gen)
+    hipLaunchKernelGGL((k_step_batch<Lat, S, C, ODD, MODE, true>), dim3(grid), dim3(b->block), 0, b->stream, mem,
+                       g.count, g.tiles);
+  else
+    hipLaunchKernelGGL((k_step_batch<Lat, S, C, ODD, MODE, false>), dim3(grid), dim3(b->block), 0, b->stream, mem,
+                       g.count, g.tiles);
+}
+
+// One step of group g: mode and parity as given.
+static void batch_launch(const lbm_batch* b, const lbm_batch::Group& g, int mode, int parity) {
   batch_types(b, [&](auto lat, auto s_t, auto c_t) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
     if (parity == 0) {
-      if (mode == kModePlain) batch_launch_mode<Lat, S, C, false, kModePlain>(b);
-      else if (mode == kModeSnapshot) batch_launch_mode<Lat, S, C, false, kModeSnapshot>(b);
-      else batch_launch_mode<Lat, S, C, false, kModeCompare>(b);
+      if (mode == kModePlain) batch_launch_mode<Lat, S, C, false, kModePlain>(b, g);
+      else if (mode == kModeSnapshot) batch_launch_mode<Lat, S, C, false, kModeSnapshot>(b, g);
+      else if (mode == kModeCompare) batch_launch_mode<Lat, S, C, false, kModeCompare>(b, g);
+      else batch_launch_mode<Lat, S, C, false, kModeSpan>(b, g);
     } else {
-      if (mode == kModePlain) batch_launch_mode<Lat, S, C, true, kModePlain>(b);
-      else if (mode == kModeSnapshot) batch_launch_mode<Lat, S, C, true, kModeSnapshot>(b);
-      else batch_launch_mode<Lat, S, C, true, kModeCompare>(b);
+      if (mode == kModePlain) batch_launch_mode<Lat, S, C, true, kModePlain>(b, g);
+      else if (mode == kModeSnapshot) batch_launch_mode<Lat, S, C, true, kModeSnapshot>(b, g);
+      else if (mode == kModeCompare) batch_launch_mode<Lat, S, C, true, kModeCompare>(b, g);
+      else batch_launch_mode<Lat, S, C, true, kModeSpan>(b, g);
     }
-    st_ = launch_check("batch step");
-    if (st_ != LBM_OK || mode != kModeCompare) return;
-    int row = 0;
-    for (int grp = 0; grp < 2; ++grp) {
-      if (b->count[grp])
-        hipLaunchKernelGGL((k_fold_members<S, C>), dim3(b->count[grp]), dim3(256), 0, b->stream,
-                           static_cast<const Member<S, C>*>(b->dev_mem[grp]), b->dev_out + (size_t)row * kPartStride);
-      row += b->count[grp];
-    }
-    st_ = launch_check("batch residual");
-    if (st_ != LBM_OK) return;
-    if (hipMemcpyAsync(b->host_out, b->dev_out, (size_t)row * kPartStride * sizeof(double), hipMemcpyDeviceToHost,
-                       b->stream) != hipSuccess)
-      st_ = fail(LBM_ERR_DEVICE, "copy of the batch residuals failed");
   });
-  return st_;
+}
+
+// Folds every member's partials of the last compare step and copies all
+// result rows to the host.
+static lbm_status batch_enqueue_fold(lbm_batch* b) {
+  batch_types(b, [&](auto, auto s_t, auto c_t) {
+    using S = decltype(s_t);
+    using C = decltype(c_t);
+    for (const auto& g : b->groups)
+      hipLaunchKernelGGL((k_fold_members<S, C>), dim3(g.count), dim3(256), 0, b->stream,
+                         static_cast<const Member<S, C>*>(b->dev_mem) + g.first,
+                         b->dev_out + (size_t)g.first * kPartStride);
+  });
+  lbm_status st_ = launch_check("batch residual");
+  if (st_ != LBM_OK) return st_;
+  HIP_TRY(hipMemcpyAsync(b->host_out, b->dev_out, b->members.size() * kPartStride * sizeof(double),
+                         hipMemcpyDeviceToHost, b->stream));
+  return LBM_OK;
+}
+
+// Steps s .. s+n-1 (n = 1, or n = K from s % K == 0) with the given start
+// parity; `modes_from` is the step whose modes the launches take (s itself, or
+// K for a captured interval).  Group-major order when n > 1.
+static lbm_status batch_enqueue(lbm_batch* b, int64_t n, int parity, int64_t modes_from) {
+  for (const auto& g : b->groups)
+    for (int64_t j = 0; j < n; ++j) batch_launch(b, g, batch_mode(b, modes_from + j), (parity + (int)j) & 1);
+  lbm_status st_ = launch_check("batch step");
+  if (st_ != LBM_OK) return st_;
+  const int m0 = batch_mode(b, modes_from);
+  if (m0 == kModeCompare || m0 == kModeSpan) return batch_enqueue_fold(b);
+  return LBM_OK;
 }
 
 // Host bookkeeping after batch step s was enqueued.
@@ -939,7 +989,7 @@ static void batch_account(lbm_batch* b, int64_t s) {
   const int mode = batch_mode(b, s);
   for (size_t i = 0; i < b->members.size(); ++i) {
     lbm_lattice* h = b->members[i];
-    if (mode == kModeCompare && b->compare_ok[i]) {
+    if ((mode == kModeCompare || mode == kModeSpan) && b->compare_ok[i]) {
       b->last_check[i] = h->t;
       b->fresh[i] = 1;
     }
@@ -947,7 +997,7 @@ static void batch_account(lbm_batch* b, int64_t s) {
     h->parity ^= 1;
     h->snapshot_valid = false;
   }
-  if (mode == kModeSnapshot)
+  if (mode == kModeSnapshot || mode == kModeSpan)
     for (size_t i = 0; i < b->members.size(); ++i)
       if (!b->compare_ok[i]) {
         b->compare_ok[i] = 1;
@@ -957,13 +1007,13 @@ static void batch_account(lbm_batch* b, int64_t s) {
   b->parity ^= 1;
 }
 
-// Captures one chunk of K steps that starts at a compare step with parity p:
-// steps K .. 2K-1 of the schedule have the modes of every later chunk.
+// Captures one check interval with start parity p.  Its launches take the modes
+// of steps K .. 2K-1, which every later interval shares; at s = 0 the compare
+// of its first step finds no member with a snapshot and steps plainly.
 static lbm_status batch_capture(lbm_batch* b, int p) {
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  lbm_status st_ = LBM_OK;
-  for (int64_t j = 0; j < b->check && st_ == LBM_OK; ++j) st_ = batch_enqueue_step(b, b->check + j, (p + (int)j) & 1);
+  lbm_status st_ = batch_enqueue(b, b->check, p, b->check);
   const hipError_t e = hipStreamEndCapture(b->stream, &g);
   if (st_ != LBM_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -993,13 +1043,10 @@ extern "C" lbm_status lbm_batch_create(void* stream, int32_t check_interval, lbm
 
 extern "C" lbm_status lbm_batch_destroy(lbm_batch* b) {
   if (!b) return LBM_OK;
-  lbm_status s = LBM_OK;
-  if (b->host_out && !b->slot.empty()) s = batch_pull(b);
-  else if (hipStreamSynchronize(b->stream) != hipSuccess) s = fail(LBM_ERR_DEVICE, "stream synchronize failed");
+  lbm_status s = batch_pull(b);
   for (lbm_lattice* h : b->members) h->batch = nullptr;
   batch_drop_graphs(b);
-  for (auto& p : b->dev_mem)
-    if (p) (void)hipFree(p);
+  if (b->dev_mem) (void)hipFree(b->dev_mem);
   if (b->dev_out) (void)hipFree(b->dev_out);
   if (b->host_out) (void)hipHostFree(b->host_out);
   if (b->staging) (void)hipHostFree(b->staging);
@@ -1063,7 +1110,15 @@ extern "C" lbm_status lbm_batch_size(const lbm_batch* b, int32_t* count) {
   return LBM_OK;
 }
 
-extern "C" lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu) {
+extern "C" lbm_status lbm_batch_member(const lbm_batch* b, int32_t index, lbm_lattice** out) {
+  if (!b || !out) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (index < 0 || index >= (int32_t)b->members.size())
+    return fail(LBM_ERR_INVALID_ARG, "member index %d out of range", index);
+  *out = b->members[(size_t)index];
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu, uint64_t group_bytes) {
   if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
   if (block != 64 && block != 128 && block != 256)
     return fail(LBM_ERR_INVALID_ARG, "block must be 64, 128 or 256 (got %d)", block);
@@ -1075,17 +1130,32 @@ extern "C" lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t 
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     b->ncu = ncu;
   }
-  if (block != b->block || blocks_per_cu != b->per_cu) {
+  if (block != b->block || blocks_per_cu != b->per_cu || group_bytes != b->group_bytes) {
     b->block = block;
     b->per_cu = blocks_per_cu;
+    b->group_bytes = group_bytes;
     b->dirty = true;
   }
   return LBM_OK;
 }
 
+extern "C" lbm_status lbm_batch_set_span(lbm_batch* b, int32_t on) {
+  if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+  if ((on != 0) == b->span) return LBM_OK;
+  if (b->s % std::max<int64_t>(b->check, 1) != 0)
+    return fail(LBM_ERR_INVALID_ARG, "the residual mode can change only at the start of a check interval");
+  b->span = on != 0;
+  // snapshots of the other mode are not comparable
+  for (auto& c : b->compare_ok) c = 0;
+  b->dirty = true;
+  batch_drop_graphs(b);
+  return LBM_OK;
+}
+
 extern "C" lbm_status lbm_batch_set_graph(lbm_batch* b, int32_t on) {
   if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
-  if (on && !b->stream) return fail(LBM_ERR_UNSUPPORTED, "graph replay needs a batch on a created stream, not the null stream");
+  if (on && !b->stream)
+    return fail(LBM_ERR_UNSUPPORTED, "graph replay needs a batch on a created stream, not the null stream");
   if (on && b->check <= 0) return fail(LBM_ERR_UNSUPPORTED, "graph replay needs a check interval > 0");
   b->use_graph = on != 0;
   if (!b->use_graph) batch_drop_graphs(b);
@@ -1097,28 +1167,29 @@ extern "C" lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_ERR_INVALID_ARG, "nsteps must be >= 0");
   if (b->members.empty() || nsteps == 0) return LBM_OK;
   int64_t left = nsteps;
+  const int64_t K = b->check;
   while (left > 0) {
     if (b->dirty) {
       lbm_status st_ = batch_upload(b);
       if (st_ != LBM_OK) return st_;
     }
-    const int64_t K = b->check;
-    if (b->use_graph && b->s % K == 0 && left >= K) {
-      // the whole chunk [s, s + K) as one replay.  Its launches are those of
-      // steps K .. 2K-1; at s = 0 its first step compares nothing (no member has
-      // a snapshot yet: the compare kernel then steps plainly).  A member whose
-      // snapshot is taken inside the chunk gets its compare flag uploaded before
-      // the next chunk.
-      if (!b->graph[b->parity]) {
-        lbm_status st_ = batch_capture(b, b->parity);
-        if (st_ != LBM_OK) return st_;
+    lbm_status st_ = LBM_OK;
+    if (K > 0 && b->s % K == 0 && left >= K) {
+      // a whole check interval, group by group.  A member whose snapshot is
+      // taken at its end gets its compare flag uploaded before the next one.
+      if (b->use_graph) {
+        if (!b->graph[b->parity]) st_ = batch_capture(b, b->parity);
+        if (st_ == LBM_OK && hipGraphLaunch(b->graph[b->parity], b->stream) != hipSuccess)
+          st_ = fail(LBM_ERR_DEVICE, "graph launch failed");
+      } else {
+        st_ = batch_enqueue(b, K, b->parity, b->s);
       }
-      HIP_TRY(hipGraphLaunch(b->graph[b->parity], b->stream));
+      if (st_ != LBM_OK) return st_;
       for (int64_t j = 0; j < K; ++j) batch_account(b, b->s);
       left -= K;
       continue;
     }
-    lbm_status st_ = batch_enqueue_step(b, b->s, b->parity);
+    st_ = batch_enqueue(b, 1, b->parity, b->s);
     if (st_ != LBM_OK) return st_;
     batch_account(b, b->s);
     left -= 1;
@@ -1143,62 +1214,70 @@ extern "C" lbm_status lbm_batch_residuals(lbm_batch* b, double* r, int64_t* at_s
   return LBM_OK;
 }
 
-extern "C" lbm_status lbm_batch_member(const lbm_batch* b, int32_t index, lbm_lattice** out) {
-  if (!b || !out) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
-  if (index < 0 || index >= (int32_t)b->members.size())
-    return fail(LBM_ERR_INVALID_ARG, "member index %d out of range", index);
-  *out = b->members[(size_t)index];
-  return LBM_OK;
-}
-
-// Times every admissible launch shape (threads per tile x resident blocks per
-// compute unit) over `steps` batch steps, after one step that absorbs the
-// descriptor upload, and keeps the fastest.  The steps are real: the members
-// advance.
-extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* block, int32_t* blocks_per_cu) {
-  if (!b || steps < 1) return fail(LBM_ERR_INVALID_ARG, "bad autotune arguments");
+// Chooses the launch shape by timing, one parameter at a time: first the group
+// size limit (from none up to 512 MiB), then the threads per tile, then the
+// persistent grid.  Each candidate runs one untimed check interval (upload,
+// caches) and one timed by HIP events; with K = 0 single steps stand in for the
+// intervals.  The steps are real: the members advance.
+extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int32_t* block, int32_t* blocks_per_cu, uint64_t* group_bytes) {
+  if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
   if (b->members.empty()) return fail(LBM_ERR_INVALID_ARG, "the batch is empty");
+  const int64_t K = b->check > 0 ? b->check : 1;
+  // reach the start of a check interval first
+  lbm_status st_ = lbm_batch_step(b, (K - b->s % K) % K);
+  if (st_ != LBM_OK) return st_;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return fail(LBM_ERR_DEVICE, "event creation failed");
   }
-  const int blocks[3] = {64, 128, 256};
-  const int per_cu[4] = {0, 4, 8, 16};
   const bool graph = b->use_graph;
   b->use_graph = false;  // time the launches themselves
-  float best = -1.0f;
-  int best_block = b->block, best_per_cu = b->per_cu;
-  lbm_status st_ = LBM_OK;
-  for (int bl : blocks) {
-    for (int pc : per_cu) {
-      if ((st_ = lbm_batch_set_launch(b, bl, pc)) != LBM_OK) break;
-      if ((st_ = lbm_batch_step(b, 1)) != LBM_OK) break;
-      (void)hipEventRecord(e0, b->stream);
-      if ((st_ = lbm_batch_step(b, steps)) != LBM_OK) break;
-      (void)hipEventRecord(e1, b->stream);
-      if (hipEventSynchronize(e1) != hipSuccess) {
-        st_ = fail(LBM_ERR_DEVICE, "event synchronize failed");
-        break;
-      }
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (best < 0.0f || ms < best) {
-        best = ms;
-        best_block = bl;
-        best_per_cu = pc;
-      }
-    }
-    if (st_ != LBM_OK) break;
+  int cur[2] = {256, 0};  // threads per tile, blocks per CU
+  uint64_t gb = 0;
+  auto trial = [&](int bl, int pc, uint64_t g, float* ms) -> lbm_status {
+    lbm_status s2 = lbm_batch_set_launch(b, bl, pc, g);
+    if (s2 == LBM_OK) s2 = lbm_batch_step(b, K);
+    if (s2 != LBM_OK) return s2;
+    if (b->dirty && (s2 = batch_upload(b)) != LBM_OK) return s2;
+    (void)hipEventRecord(e0, b->stream);
+    if ((s2 = lbm_batch_step(b, K)) != LBM_OK) return s2;
+    (void)hipEventRecord(e1, b->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(LBM_ERR_DEVICE, "event synchronize failed");
+    (void)hipEventElapsedTime(ms, e0, e1);
+    return LBM_OK;
+  };
+  const uint64_t MiB = 1ull << 20;
+  const uint64_t groups_c[6] = {0, 32 * MiB, 64 * MiB, 128 * MiB, 256 * MiB, 512 * MiB};
+  const int blocks_c[3] = {64, 128, 256};
+  const int per_cu_c[3] = {0, 4, 8};
+  float best = -1.0f, ms = 0.0f;
+  for (uint64_t g : groups_c) {
+    if ((st_ = trial(cur[0], cur[1], g, &ms)) != LBM_OK) break;
+    if (best < 0.0f || ms < best) best = ms, gb = g;
   }
+  const int start[2] = {cur[0], cur[1]};  // measured already
+  if (st_ == LBM_OK)
+    for (int bl : blocks_c) {
+      if (bl == start[0]) continue;
+      if ((st_ = trial(bl, cur[1], gb, &ms)) != LBM_OK) break;
+      if (ms < best) best = ms, cur[0] = bl;
+    }
+  if (st_ == LBM_OK)
+    for (int pc : per_cu_c) {
+      if (pc == start[1]) continue;
+      if ((st_ = trial(cur[0], pc, gb, &ms)) != LBM_OK) break;
+      if (ms < best) best = ms, cur[1] = pc;
+    }
   b->use_graph = graph;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st_ != LBM_OK) return st_;
-  if (block) *block = best_block;
-  if (blocks_per_cu) *blocks_per_cu = best_per_cu;
-  return lbm_batch_set_launch(b, best_block, best_per_cu);
+  if (block) *block = cur[0];
+  if (blocks_per_cu) *blocks_per_cu = cur[1];
+  if (group_bytes) *group_bytes = gb;
+  return lbm_batch_set_launch(b, cur[0], cur[1], gb);
 }
 
 extern "C" const char* lbm_status_string(lbm_status s) {

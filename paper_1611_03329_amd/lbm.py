@@ -104,6 +104,7 @@ _lib.lbm_status_string.argtypes = [ctypes.c_int]
 _lib.lbm_status_string.restype = ctypes.c_char_p
 _lib.lbm_last_error.argtypes = []
 _lib.lbm_last_error.restype = ctypes.c_char_p
+_lib.lbm_transfer_state.argtypes = [_V, _V]
 _lib.lbm_batch_create.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_V)]
 _lib.lbm_batch_destroy.argtypes = [_V]
 _lib.lbm_batch_add.argtypes = [_V, _V]
@@ -112,15 +113,17 @@ _lib.lbm_batch_size.argtypes = [_V, ctypes.POINTER(ctypes.c_int32)]
 _lib.lbm_batch_member.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_V)]
 _lib.lbm_batch_step.argtypes = [_V, ctypes.c_int64]
 _lib.lbm_batch_residuals.argtypes = [_V, _D, _I64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
-_lib.lbm_batch_set_launch.argtypes = [_V, ctypes.c_int32, ctypes.c_int32]
-_lib.lbm_batch_autotune.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                                    ctypes.POINTER(ctypes.c_int32)]
+_lib.lbm_batch_set_launch.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64]
+_lib.lbm_batch_autotune.argtypes = [_V, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_uint64)]
 _lib.lbm_batch_set_graph.argtypes = [_V, ctypes.c_int32]
+_lib.lbm_batch_set_span.argtypes = [_V, ctypes.c_int32]
 for _name in ("lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_step",
               "lbm_time", "lbm_derived_params", "lbm_fields", "lbm_nusselt", "lbm_residual",
-              "lbm_totals", "lbm_get_state", "lbm_set_state", "lbm_batch_create", "lbm_batch_destroy",
+              "lbm_totals", "lbm_get_state", "lbm_set_state", "lbm_transfer_state", "lbm_batch_create", "lbm_batch_destroy",
               "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size", "lbm_batch_member", "lbm_batch_step",
-              "lbm_batch_residuals", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_set_graph"):
+              "lbm_batch_residuals", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_set_graph",
+              "lbm_batch_set_span"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -279,6 +282,11 @@ class Lattice:
         self._settle()
         return f, g
 
+    def transfer_from(self, other: "Lattice"):
+        """Takes over the state of ``other`` (same lattice type, shape and rest
+        state), converting its storage precision."""
+        _check(_lib.lbm_transfer_state(self._h, other._h))
+
     def set_state(self, f, g):
         f = torch.as_tensor(f, dtype=torch.float64).to(self.device).contiguous()
         g = torch.as_tensor(g, dtype=torch.float64).to(self.device).contiguous()
@@ -295,7 +303,8 @@ class Batch:
     graph, which needs a stream of its own: one is created when none is given."""
 
     def __init__(self, check_interval: int, stream: torch.cuda.Stream | None = None, graph: bool = False,
-                 block: int | None = None, per_cu: int = 0, device=None):
+                 block: int | None = None, per_cu: int = 0, group_bytes: int = 0, span: bool = False,
+                 device=None):
         self.device = torch.device("cuda") if device is None else torch.device(device)
         if stream is None:
             stream = torch.cuda.Stream(self.device) if graph else torch.cuda.current_stream(self.device)
@@ -305,10 +314,12 @@ class Batch:
         _check(_lib.lbm_batch_create(ctypes.c_void_p(stream.cuda_stream), self.check_interval, ctypes.byref(h)))
         self._h = h
         self.members: list[Lattice] = []
-        if block is not None or per_cu:
-            self.set_launch(256 if block is None else block, per_cu)
+        if block is not None or per_cu or group_bytes:
+            self.set_launch(256 if block is None else block, per_cu, group_bytes)
         if graph:
             _check(_lib.lbm_batch_set_graph(self._h, 1))
+        if span:
+            self.set_span(True)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -347,17 +358,23 @@ class Batch:
     def step(self, n: int = 1):
         _check(_lib.lbm_batch_step(self._h, int(n)))
 
-    def set_launch(self, block: int, per_cu: int = 0):
-        """Threads per tile and resident blocks per compute unit (0: one block per tile)."""
-        _check(_lib.lbm_batch_set_launch(self._h, int(block), int(per_cu)))
+    def set_span(self, on: bool):
+        """Residual over the whole check interval (True) or over one step."""
+        _check(_lib.lbm_batch_set_span(self._h, int(bool(on))))
 
-    def autotune(self, steps: int = 20):
-        """Times every launch shape over ``steps`` real steps; returns the
-        chosen (block, per_cu)."""
+    def set_launch(self, block: int, per_cu: int = 0, group_bytes: int = 0):
+        """Threads per tile, resident blocks per compute unit (0: one block per
+        tile) and the group size limit in bytes (0: no limit)."""
+        _check(_lib.lbm_batch_set_launch(self._h, int(block), int(per_cu), int(group_bytes)))
+
+    def autotune(self):
+        """Times launch shapes over real check intervals; returns the chosen
+        (block, per_cu, group_bytes)."""
         b = ctypes.c_int32()
         c = ctypes.c_int32()
-        _check(_lib.lbm_batch_autotune(self._h, int(steps), ctypes.byref(b), ctypes.byref(c)))
-        return int(b.value), int(c.value)
+        g = ctypes.c_uint64()
+        _check(_lib.lbm_batch_autotune(self._h, ctypes.byref(b), ctypes.byref(c), ctypes.byref(g)))
+        return int(b.value), int(c.value), int(g.value)
 
     def residuals(self):
         """(r, at_step, unstable) lists in member order."""

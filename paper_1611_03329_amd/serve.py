@@ -56,6 +56,7 @@ class Result:
     converged: bool = False
     unstable: bool = False
     nu: tuple = ()          # face Nusselt numbers at retirement
+    promoted_at: int = -1   # steps taken in FP16 storage before the move to FP32
 
     @property
     def latency(self) -> float:
@@ -82,30 +83,65 @@ def _done(res: Result, r: float, at: int, unstable: bool, steps: int, tol: float
 
 
 class Server:
-    """Continuous-batching solve server on the current device."""
+    """Continuous-batching solve server on the current device.
+
+    precision "fp32": every solve in FP32 storage, checked every
+    `check_interval` steps with the one-step residual.
+
+    precision "fp16": a solve starts in FP16 storage (136 instead of 208 bytes
+    per node and step).  FP16 rounding of the stored populations puts a floor
+    under the one-step residual (about 2e-4 to 7e-3 relative on the cavity
+    workloads), so the FP16 phase is watched with the residual over a whole
+    interval of `fp16_interval` steps (lbm_batch_set_span), whose rounding
+    floor divided by the interval is that many times lower.  When that
+    per-step rate falls below `promote_rate`, or stops falling (no new low by
+    the factor plateau[0] within plateau[1] checks), the solve moves to FP32
+    storage (lbm_transfer_state, exact) and finishes there with the one-step
+    residual.  The move is decided from the solve's own residuals at an
+    interval boundary, and the FP32 lattice starts its own check schedule at
+    time 0, so results stay independent of the mix.
+
+    Every batch advances `chunk` steps per round trip (the FP16 interval in
+    fp16 mode, else `check_interval`); admission and retirement happen between
+    chunks, where every batch's step counter is a multiple of its interval."""
 
     def __init__(self, precision: str = "fp16", check_interval: int = 100, tol: float = 1e-6,
                  max_steps: int = 200_000, hbm_budget: int | None = None, max_members: int = 256,
-                 graph: bool = True, launch: tuple | None = None, device=None):
+                 graph: bool = True, launch: tuple | None = None, fp16_interval: int = 500,
+                 promote_rate: float = 1e-5, plateau: tuple = (0.9, 3), device=None):
         if check_interval <= 0 or check_interval % 2:
             raise ValueError("check_interval must be a positive even number (chunks keep the parity)")
+        if precision not in ("fp32", "fp16"):
+            raise ValueError("precision must be fp32 or fp16")
+        if precision == "fp16" and fp16_interval % check_interval:
+            raise ValueError("fp16_interval must be a multiple of check_interval")
         self.precision = precision
         self.K = int(check_interval)
+        self.K16 = int(fp16_interval)
+        self.chunk = self.K16 if precision == "fp16" else self.K
         self.tol = float(tol)
         self.max_steps = int(max_steps)
+        self.promote_rate = float(promote_rate)
+        self.plateau = (float(plateau[0]), int(plateau[1]))
         self.device = torch.device("cuda") if device is None else torch.device(device)
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info(self.device)
             hbm_budget = int(0.8 * free)
         self.hbm_budget = int(hbm_budget)
         self.max_members = int(max_members)
-        self.batch = Batch(self.K, graph=graph, device=self.device)
+        # one batch per storage precision, each on a stream of its own
+        self.batches = {"fp32": Batch(self.K, graph=graph, device=self.device)}
+        if precision == "fp16":
+            self.batches["fp16"] = Batch(self.K16, graph=graph, span=True, device=self.device)
         if launch is not None:
-            self.batch.set_launch(*launch)
-        self.stats = {"chunks": 0, "lattice_steps": 0, "node_steps": 0, "peak_members": 0, "peak_bytes": 0}
+            for b in self.batches.values():
+                b.set_launch(*launch)
+        self.stats = {"chunks": 0, "lattice_steps": 0, "node_steps": 0, "peak_members": 0, "peak_bytes": 0,
+                      "promoted": 0}
 
     def close(self):
-        self.batch.close()
+        for b in self.batches.values():
+            b.close()
 
     def __enter__(self):
         return self
@@ -113,59 +149,116 @@ class Server:
     def __exit__(self, *a):
         self.close()
 
-    def run(self, requests: list, clock=time.perf_counter) -> list:
+    def run(self, requests: list, clock=time.perf_counter, progress=None) -> list:
         """Serves `requests` (arrival times relative to the call) to completion;
-        returns one Result per request, in request order."""
+        returns one Result per request, in request order.  `progress`, if
+        given, is called with a one-line status after every retirement."""
+        first = self.precision
         pending = deque(sorted(requests, key=lambda q: q.arrival))
-        need = {q.rid: required_bytes(make_params(q.workload, self.precision, self.K)) for q in requests}
+        need = {}
         for q in requests:
-            if need[q.rid] > self.hbm_budget:
-                raise ValueError(f"request {q.rid} needs {need[q.rid]} B, more than the HBM budget")
+            need[q.rid] = {p: required_bytes(make_params(q.workload, p, self.K)) for p in self.batches}
+            # an FP16 solve reserves room for its FP32 copy as well, so that its
+            # move can never wait for memory
+            need[q.rid]["admit"] = sum(need[q.rid].values()) if first == "fp16" else need[q.rid]["fp32"]
+            if need[q.rid]["admit"] > self.hbm_budget:
+                raise ValueError(f"request {q.rid} needs more than the HBM budget")
         waiting = deque()
-        active = {}   # id(lattice) -> (lattice, Result, bytes)
+        active = {}   # id(lattice) -> entry
         results = {}
         used = 0
         t0 = clock()
+
+        def retire(lat, e):
+            nonlocal used
+            res = e["res"]
+            if not res.unstable:
+                res.nu = tuple(lat.nusselt())
+            res.finished = clock() - t0
+            lat.close()
+            del active[id(lat)]
+            used -= e["bytes"]
+            results[res.rid] = res
+            if progress is not None:
+                progress(f"{len(results)}/{len(requests)} done at {res.finished:.1f}s: {res.name} "
+                         f"steps {res.steps} r {res.residual:.2e} active {len(active)}")
+
         while pending or waiting or active:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             # admission, first come first served, between chunks
-            while waiting and len(active) < self.max_members and used + need[waiting[0].rid] <= self.hbm_budget:
+            while (waiting and len(active) < self.max_members
+                   and used + need[waiting[0].rid]["admit"] <= self.hbm_budget):
                 q = waiting.popleft()
-                lat = Lattice(q.workload, self.precision, device=self.device)
-                self.batch.add(lat)
+                lat = Lattice(q.workload, first, device=self.device)
+                self.batches[first].add(lat)
                 res = Result(q.rid, q.workload.get("name", ""), lat.nodes, q.arrival, admitted=clock() - t0)
-                active[id(lat)] = (lat, res, need[q.rid])
-                used += need[q.rid]
+                active[id(lat)] = {"lat": lat, "res": res, "bytes": need[q.rid]["admit"], "q": q, "prec": first,
+                                   "base": 0, "best": math.inf, "since": 0}
+                used += need[q.rid]["admit"]
             self.stats["peak_members"] = max(self.stats["peak_members"], len(active))
             self.stats["peak_bytes"] = max(self.stats["peak_bytes"], used)
             if not active:
                 if pending:
                     time.sleep(max(0.0, pending[0].arrival - (clock() - t0)))
                 continue
-            self.batch.step(self.K)
+            for b in self.batches.values():
+                if len(b):
+                    b.step(self.chunk)
             self.stats["chunks"] += 1
-            nodes = sum(v[0].nodes for v in active.values())
-            self.stats["lattice_steps"] += self.K * len(active)
-            self.stats["node_steps"] += self.K * nodes
-            r, at, un = self.batch.residuals()
-            for lat, rr, aa, uu in list(zip(list(self.batch.members), r, at, un)):
-                _, res, nb = active[id(lat)]
-                if _done(res, rr, aa, uu, lat.time, self.tol, self.max_steps):
-                    self.batch.remove(lat)
-                    if not res.unstable:
-                        res.nu = tuple(lat.nusselt())
-                    res.finished = clock() - t0
-                    lat.close()
-                    del active[id(lat)]
-                    used -= nb
-                    results[res.rid] = res
+            self.stats["lattice_steps"] += self.chunk * len(active)
+            self.stats["node_steps"] += self.chunk * sum(e["lat"].nodes for e in active.values())
+            promote = []
+            for prec, b in self.batches.items():
+                if not len(b):
+                    continue
+                r, at, un = b.residuals()
+                for lat, rr, aa, uu in list(zip(list(b.members), r, at, un)):
+                    e = active[id(lat)]
+                    res = e["res"]
+                    steps = e["base"] + lat.time
+                    if prec == "fp16":
+                        res.steps = steps
+                        if uu:
+                            res.unstable = True
+                        if uu or steps >= self.max_steps:
+                            b.remove(lat)
+                            retire(lat, e)
+                            continue
+                        if aa <= 0:
+                            continue
+                        rate = rr / self.K16
+                        if rate < e["best"] * self.plateau[0]:
+                            e["best"], e["since"] = rate, 0
+                        else:
+                            e["since"] += 1
+                        if rate < self.promote_rate or e["since"] >= self.plateau[1]:
+                            promote.append(lat)
+                    elif _done(res, rr, aa, uu, steps, self.tol, self.max_steps):
+                        b.remove(lat)
+                        retire(lat, e)
+            for lat in promote:
+                e = active[id(lat)]
+                n32 = need[e["q"].rid]["fp32"]
+                new = Lattice(e["q"].workload, "fp32", device=self.device)
+                new.transfer_from(lat)
+                self.batches["fp16"].remove(lat)
+                e["res"].promoted_at = e["base"] + lat.time
+                e["base"] += lat.time
+                lat.close()
+                del active[id(lat)]
+                self.batches["fp32"].add(new)
+                # the FP16 lattice's share of the reservation is free again
+                used -= e["bytes"] - n32
+                e.update(lat=new, bytes=n32, prec="fp32")
+                active[id(new)] = e
+                self.stats["promoted"] += 1
         return [results[q.rid] for q in requests]
 
 
 def solve_sequential(requests: list, precision: str = "fp32", check_interval: int = 100, tol: float = 1e-6,
-                     max_steps: int = 200_000, clock=time.perf_counter, device=None) -> list:
+                     max_steps: int = 200_000, clock=time.perf_counter, device=None, progress=None) -> list:
     """The baseline: each request alone on its own lattice (lbm_step), one after
     another in arrival order, with the same check schedule and stopping rule."""
     K = int(check_interval)
@@ -195,6 +288,9 @@ def solve_sequential(requests: list, precision: str = "fp32", check_interval: in
         res.finished = clock() - t0
         lat.close()
         out.append(res)
+        if progress is not None:
+            progress(f"{len(out)}/{len(requests)} done at {res.finished:.1f}s: {res.name} steps {res.steps} "
+                     f"r {res.residual:.2e}")
     order = {q.rid: i for i, q in enumerate(requests)}
     return sorted(out, key=lambda r: order[r.rid])
 

@@ -73,16 +73,22 @@ def _same(a, b):
     return torch.equal(fa, fb) and torch.equal(ga, gb)
 
 
-@pytest.mark.parametrize("prec,block,per_cu", [("fp64", 256, 0), ("fp32", 64, 0), ("fp16", 128, 0),
-                                                ("fp32", 256, 1), ("fp16", 64, 4)])
-def test_batch_members_match_solo_bitwise(prec, block, per_cu):
-    """Each member of a mixed batch (lean and general wall rules, four sizes)
-    equals the same lattice stepped alone, bit for bit, at both parities, with
-    one block per tile or a persistent grid (per_cu > 0)."""
-    _say(f"case batch-vs-solo {prec} block {block} per_cu {per_cu}")
+MiB = 1 << 20
+
+
+@pytest.mark.parametrize("prec,block,per_cu,group", [
+    ("fp64", 256, 0, 0), ("fp32", 64, 0, 0), ("fp16", 128, 0, 0), ("fp32", 256, 1, 0), ("fp16", 64, 4, 0),
+    ("fp32", 256, 0, MiB), ("fp64", 128, 4, 2 * MiB)])
+def test_batch_members_match_solo_bitwise(prec, block, per_cu, group):
+    """Each member of a mixed batch (lean and general wall rules, five sizes)
+    equals the same lattice stepped alone, bit for bit, at both parities: with
+    one block per tile or a persistent grid (per_cu > 0), and with the members
+    in one group per wall-rule set or split into groups of at most `group`
+    bytes that run whole check intervals one after another."""
+    _say(f"case batch-vs-solo {prec} block {block} per_cu {per_cu} group {group}")
     ms = _members()
     solo = {k: _make(wl, sd, prec, 0) for k, (wl, sd) in ms.items()}
-    with Batch(check_interval=6, block=block, per_cu=per_cu) as b:
+    with Batch(check_interval=6, block=block, per_cu=per_cu, group_bytes=group) as b:
         mem = {k: _make(wl, sd, prec, 0) for k, (wl, sd) in ms.items()}
         for k in ms:
             b.add(mem[k])
@@ -215,12 +221,13 @@ def test_join_and_leave_mid_schedule():
             x.close()
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("group", [0, MiB])
+def test_graph_replay_matches_eager(group):
     """Check intervals replayed from a HIP graph give the eager results on every
     replay, with eager work and synchronizations between the replays."""
-    _say("case graph replay fp32 K=8")
+    _say(f"case graph replay fp32 K=8 group {group}")
     ms = _members()
-    with Batch(check_interval=8, graph=True) as gb, Batch(check_interval=8) as eb:
+    with Batch(check_interval=8, graph=True, group_bytes=group) as gb, Batch(check_interval=8) as eb:
         g = {k: _make(w, s, "fp32", 0) for k, (w, s) in ms.items()}
         e = {k: _make(w, s, "fp32", 0) for k, (w, s) in ms.items()}
         for k in ms:
@@ -256,11 +263,12 @@ def test_autotune_keeps_results():
         mem = {k: _make(w, s, "fp32", 0) for k, (w, s) in ms.items()}
         for k in ms:
             b.add(mem[k])
-        block, per_cu = b.autotune(steps=5)
-        assert block in (64, 128, 256) and per_cu in (0, 4, 8, 16)
+        block, per_cu, group = b.autotune()
+        assert block in (64, 128, 256) and per_cu in (0, 4, 8)
+        assert group in (0, 32 * MiB, 64 * MiB, 128 * MiB, 256 * MiB)
         b.step(4)
         steps = mem["cavity"].time
-        assert steps == 12 * 6 + 4
+        assert steps == 10 * 2 * 10 + 4   # 10 candidates, one untimed and one timed interval each
         for k, (w, s) in ms.items():
             ref = _make(w, s, "fp32", 0)
             ref.step(steps)
@@ -310,3 +318,55 @@ def test_batch_rejects_mixed_precision_and_bad_block():
             b.add(a)
         a.close()
         c.close()
+
+
+@pytest.mark.parametrize("src_prec,dst_prec", [("fp16", "fp32"), ("fp32", "fp64"), ("fp32", "fp32")])
+def test_transfer_state_converts_precision(src_prec, dst_prec):
+    """lbm_transfer_state copies the logical state across precisions (from an
+    odd time, i.e. the other storage parity): the destination's state equals
+    the source's exactly (every value is representable), and an FP32 copy of
+    an FP32 lattice continues on the same trajectory."""
+    _say(f"case transfer {src_prec} -> {dst_prec}")
+    wl, sd = _members()["big"]
+    src = _make(wl, sd, src_prec, 0)
+    src.step(5)
+    dst = _make(wl, sd, dst_prec, 0)
+    dst.transfer_from(src)
+    fs, gs = _state(src)
+    fd, gd = _state(dst)
+    assert torch.equal(fs, fd) and torch.equal(gs, gd)
+    if src_prec == dst_prec:
+        src.step(6)
+        dst.step(6)
+        fs, gs = _state(src)
+        fd, gd = _state(dst)
+        assert torch.allclose(fd, fs, rtol=1e-6, atol=0) and torch.allclose(gd, gs, rtol=1e-6, atol=1e-9)
+    src.close()
+    dst.close()
+
+
+def test_span_residual_matches_oracle():
+    """With the span residual the check at step 8 (interval 4) compares the
+    state with that of step 4: r equals the definition applied to oracle
+    fields at 4 and 8.  Graph replay and group size do not change it."""
+    _say("case span residual fp64 K=4")
+    wl, sd = _members()["lid"]
+    with oracle.Oracle(wl) as o:
+        f0, g0 = lbm_inputs.random_state(wl["q"], o.shape, sd, amp=0.05, T_amp=0.4)
+        o.set_state(f0, g0)
+        o.step(4)
+        a = o.fields()
+        o.step(4)
+        r_ref = _theta_residual(a, o.fields(), wl)
+    out = []
+    for graph in (False, True):
+        with Batch(check_interval=4, span=True, graph=graph) as b:
+            lat = _make(wl, sd, "fp64", 0)
+            b.add(lat)
+            b.step(9)
+            r, at, un = b.residuals()
+            assert at == [8] and not un[0]
+            assert abs(r[0] - r_ref) <= 1e-9 * r_ref, (r[0], r_ref)
+            out.append(r[0])
+            lat.close()
+    assert out[0] == out[1]

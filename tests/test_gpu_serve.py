@@ -47,9 +47,12 @@ def test_results_are_the_same_alone_and_in_the_mix(prec):
         assert srv.stats["peak_members"] >= 2
     for q, m in zip(reqs, mix):
         assert m.converged, (q.rid, m.residual, m.steps)
+        # FP16 storage stalls above the tolerance: every solve finishes in FP32
+        assert (m.promoted_at > 0) == (prec == "fp16"), (q.rid, m.promoted_at)
         with Server(prec, graph=True, **KW) as srv1:
             (a,) = srv1.run([Request(q.rid, 0.0, q.workload)])
-        assert (a.steps, a.checked_at, a.residual, a.nu) == (m.steps, m.checked_at, m.residual, m.nu), q.rid
+        assert ((a.steps, a.checked_at, a.residual, a.nu, a.promoted_at)
+                == (m.steps, m.checked_at, m.residual, m.nu, m.promoted_at)), q.rid
     s = summarize(mix)
     _say(f"{prec}: {s}")
     assert s["converged"] == len(reqs)
@@ -75,10 +78,10 @@ def test_admission_respects_the_hbm_budget():
     """With room for about two of the requests at a time the server never holds
     more than the budget, and still completes every request."""
     reqs = _requests()
-    need = sorted(required_bytes(make_params(q.workload, "fp16", 100)) for q in reqs)
+    need = sorted(required_bytes(make_params(q.workload, "fp32", 100)) for q in reqs)
     budget = need[-1] + need[-2]
     _say(f"case admission budget {budget} B")
-    with Server("fp16", hbm_budget=budget, **KW) as srv:
+    with Server("fp32", hbm_budget=budget, **KW) as srv:
         res = srv.run(reqs)
         assert srv.stats["peak_bytes"] <= budget
         assert srv.stats["peak_members"] <= 3
@@ -86,3 +89,17 @@ def test_admission_respects_the_hbm_budget():
     # first come, first served: admission times follow arrival order
     adm = [r.admitted for r in sorted(res, key=lambda r: r.arrival)]
     assert adm == sorted(adm)
+
+
+def test_fp16_promotion_respects_the_budget():
+    """An FP16 solve is admitted with room for its FP32 copy, so its move never
+    waits and the reservations never exceed the budget."""
+    reqs = _requests()
+    both = sorted(sum(required_bytes(make_params(q.workload, p, 100)) for p in ("fp16", "fp32")) for q in reqs)
+    budget = both[-1] + both[-2]
+    _say(f"case fp16 promotion budget {budget} B")
+    with Server("fp16", hbm_budget=budget, **KW) as srv:
+        res = srv.run(reqs)
+        assert srv.stats["peak_bytes"] <= budget
+        assert srv.stats["promoted"] == len(reqs)
+    assert all(r.converged for r in res)
