@@ -153,3 +153,26 @@ def config_serving(count: int = 64, rate: float = 20.0, seed: int = 5, edge_rang
     lo, hi = np.log(edge_range[0]), np.log(edge_range[1])
     edges = np.rint(np.exp(rng.uniform(lo, hi, size=count))).astype(int)
     return [(float(t[i]), _cavity_draw(rng, int(edges[i]), i, seed)) for i in range(count)]
+
+
+def melting(nx: int = 400, ny: int = 6, nz: int = 6, *, alpha_ratio: float = 1.0, alpha_s: float = 0.02,
+            stefan: float = 1.0, T_hot: float = 1.0, T_melt: float = 0.0, T_init: float = -1.0,
+            porosity: float = 1.0, c_pl: float = 1.0, c_ps: float = 1.0, matrix_heat: float = 0.0,
+            varpi: float = 0.5, mushy: float = 0.0) -> dict:
+    """Two-region conduction melting in a semi-infinite slab (the setting of
+    Sec. 4.3): solid at T_init, the -x wall held at T_hot > T_melt from t = 0,
+    the +x wall at T_init, periodic in y and z, no flow.  alpha_l =
+    alpha_ratio * alpha_s; latent heat from the Stefan number St = c_pl (T_hot
+    - T_melt) / L_a.  ``mushy`` > 0 spreads melting over [T_melt, T_melt +
+    mushy]."""
+    return {
+        "name": f"melting{nx}x{ny}x{nz}_ratio{alpha_ratio:g}", "energy": "enthalpy",
+        "nx": int(nx), "ny": int(ny), "nz": int(nz), "varpi": float(varpi), "porosity": float(porosity),
+        "c_pl": float(c_pl), "c_ps": float(c_ps), "matrix_heat": float(matrix_heat),
+        "latent": float(c_pl * (T_hot - T_melt) / stefan), "T_solidus": float(T_melt),
+        "T_liquidus": float(T_melt + mushy), "alpha_l": float(alpha_ratio * alpha_s), "alpha_s": float(alpha_s),
+        "zeta_e": 1.2, "zeta_nu": 1.2, "T_init": float(T_init),
+        "faces": [face("wall", "isothermal", T_hot), face("wall", "isothermal", T_init),
+                  face("periodic", "periodic"), face("periodic", "periodic"),
+                  face("periodic", "periodic"), face("periodic", "periodic")],
+    }

@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+_SRC_ENTH = os.path.join(_HERE, "enthalpy_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FACE_NAMES = ("-x", "+x", "-y", "+y", "-z", "+z")
@@ -32,7 +33,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
-               "-Wall", "-Wextra", "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"]
+               "-Wall", "-Wextra", "-Wno-unused-parameter", _SRC, _SRC_ENTH, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -336,3 +337,103 @@ class Oracle:
                                       _ptr(fo), _ptr(go), _ptr(rho), _ptr(u), _ptr(T), _ptr(F)),
                "collide_node")
         return fo, go, {"rho": rho[0], "u": u, "T": T[0], "F": F}
+
+
+# ---------------------------------------------------------------- enthalpy model (App. B)
+class _EnthParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("varpi", ctypes.c_double), ("porosity", ctypes.c_double),
+        ("c_pl", ctypes.c_double), ("c_ps", ctypes.c_double), ("matrix_heat", ctypes.c_double),
+        ("latent", ctypes.c_double), ("T_solidus", ctypes.c_double), ("T_liquidus", ctypes.c_double),
+        ("alpha_l", ctypes.c_double), ("alpha_s", ctypes.c_double),
+        ("zeta_e", ctypes.c_double), ("zeta_nu", ctypes.c_double),
+        ("heat", ctypes.c_int32 * 6), ("T_wall", ctypes.c_double * 6),
+        ("T_init", ctypes.c_double),
+    ]
+
+
+def _enth_lib():
+    L = lib()
+    if not getattr(L, "_enth_ready", False):
+        L.ref_enthalpy_create.argtypes = [ctypes.POINTER(_EnthParams), ctypes.POINTER(ctypes.c_void_p)]
+        L.ref_enthalpy_destroy.argtypes = [ctypes.c_void_p]
+        L.ref_enthalpy_destroy.restype = None
+        L.ref_enthalpy_time.argtypes = [ctypes.c_void_p]
+        L.ref_enthalpy_time.restype = ctypes.c_int64
+        L.ref_enthalpy_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.ref_enthalpy_fields.argtypes = [ctypes.c_void_p, _D, _D, _D]
+        L.ref_enthalpy_get_state.argtypes = [ctypes.c_void_p, _D]
+        L.ref_enthalpy_set_state.argtypes = [ctypes.c_void_p, _D]
+        L.ref_enthalpy_phase.argtypes = [ctypes.c_void_p, ctypes.c_double, _D, _D]
+        L._enth_ready = True
+    return L
+
+
+def enthalpy_params_from_workload(wl: dict) -> _EnthParams:
+    p = _EnthParams()
+    p.nx, p.ny, p.nz = wl["nx"], wl["ny"], wl["nz"]
+    for k in ("varpi", "porosity", "c_pl", "c_ps", "matrix_heat", "latent", "T_solidus", "T_liquidus",
+              "alpha_l", "alpha_s", "zeta_e", "zeta_nu", "T_init"):
+        setattr(p, k, float(wl[k]))
+    for f, fc in enumerate(wl["faces"]):
+        p.heat[f] = HEAT[fc["heat"]]
+        p.T_wall[f] = float(fc.get("T_wall", 0.0))
+    return p
+
+
+class EnthalpyOracle:
+    """The enthalpy-based D3Q7-MRT model of App. B with u = 0 (Sec. 4.3)."""
+
+    def __init__(self, workload: dict):
+        self._lib = _enth_lib()
+        self.params = enthalpy_params_from_workload(workload)
+        self.shape = (workload["nz"], workload["ny"], workload["nx"])
+        self.n = workload["nx"] * workload["ny"] * workload["nz"]
+        h = ctypes.c_void_p()
+        _check(self._lib.ref_enthalpy_create(ctypes.byref(self.params), ctypes.byref(h)), "ref_enthalpy_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ref_enthalpy_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def time(self) -> int:
+        return int(self._lib.ref_enthalpy_time(self._h))
+
+    def step(self, n: int = 1):
+        _check(self._lib.ref_enthalpy_step(self._h, int(n)), "ref_enthalpy_step")
+
+    def fields(self) -> dict:
+        out = {k: np.empty(self.shape) for k in ("T", "En", "fl")}
+        _check(self._lib.ref_enthalpy_fields(self._h, _ptr(out["T"]), _ptr(out["En"]), _ptr(out["fl"])),
+               "ref_enthalpy_fields")
+        return out
+
+    def get_state(self) -> np.ndarray:
+        g = np.empty((7,) + self.shape)
+        _check(self._lib.ref_enthalpy_get_state(self._h, _ptr(g)), "ref_enthalpy_get_state")
+        return g
+
+    def set_state(self, g):
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        assert g.shape == (7,) + self.shape
+        _check(self._lib.ref_enthalpy_set_state(self._h, _ptr(g)), "ref_enthalpy_set_state")
+
+    def phase(self, En: float):
+        T = ctypes.c_double()
+        fl = ctypes.c_double()
+        _check(self._lib.ref_enthalpy_phase(self._h, float(En), ctypes.byref(T), ctypes.byref(fl)),
+               "ref_enthalpy_phase")
+        return T.value, fl.value

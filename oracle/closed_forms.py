@@ -88,3 +88,42 @@ def mixed_convection_accel(n: int, u1: float, nu: float, K: float, gbeta: float,
 def relative_global_error(a: np.ndarray, b: np.ndarray) -> float:
     """Eq. 52: E = sqrt(sum |a - b|^2) / sqrt(sum |a|^2), a the analytical field."""
     return float(np.sqrt(np.sum((a - b) ** 2)) / np.sqrt(np.sum(a ** 2)))
+
+
+# ---------------------------------------------------------------- two-region melting (Sec. 4.3)
+def melting_eta(alpha_l: float, alpha_s: float, k_l: float, k_s: float, T_hot: float, T_melt: float,
+                T_init: float, latent: float, c_pl: float) -> float:
+    """Root eta of the transcendental Eq. 59 of the two-region melting problem
+    (bisection on the bracket where its two sides cross)."""
+    from scipy.special import erf, erfc
+    r = alpha_l / alpha_s
+    theta = (T_init - T_melt) / (T_hot - T_melt)
+
+    def residual(eta):
+        lhs = (np.exp(-eta * eta) / erf(eta)
+               + (k_s / k_l) * np.sqrt(r) * theta * np.exp(-eta * eta * r) / erfc(eta * np.sqrt(r)))
+        return lhs - eta * latent * np.sqrt(np.pi) / (c_pl * (T_hot - T_melt))
+
+    lo, hi = 1e-6, 1.0
+    while residual(hi) > 0.0:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if residual(mid) > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def two_region_melting(x, t: float, alpha_l: float, alpha_s: float, k_l: float, k_s: float, T_hot: float,
+                       T_melt: float, T_init: float, latent: float, c_pl: float):
+    """Temperature of Eqs. 57 (liquid, x <= x_m) and 58 (solid) and the front
+    x_m(t) = 2 eta sqrt(alpha_l t), with eta from Eq. 59."""
+    from scipy.special import erf, erfc
+    eta = melting_eta(alpha_l, alpha_s, k_l, k_s, T_hot, T_melt, T_init, latent, c_pl)
+    x = np.asarray(x, dtype=np.float64)
+    xm = 2.0 * eta * np.sqrt(alpha_l * t)
+    liquid = T_hot - (T_hot - T_melt) * erf(x / (2.0 * np.sqrt(alpha_l * t))) / erf(eta)
+    solid = T_init + (T_melt - T_init) * erfc(x / (2.0 * np.sqrt(alpha_s * t))) / erfc(eta * np.sqrt(alpha_l / alpha_s))
+    return np.where(x <= xm, liquid, solid), xm, eta

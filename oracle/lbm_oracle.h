@@ -140,6 +140,35 @@ int ref_threads(void);
 uint64_t ref_splitmix64(uint64_t state);
 double ref_noise(uint64_t seed, uint64_t n, double amp);
 
+/* ---- enthalpy-based D3Q7-MRT model, App. B, conduction only (enthalpy_oracle.c) */
+typedef struct {
+  int32_t nx, ny, nz;
+  double varpi;                 /* csT^2 = varpi/3 (Eq. 40) */
+  double porosity;              /* phi of Eq. B4 */
+  double c_pl, c_ps;            /* specific heats of the liquid and the solid */
+  double matrix_heat;           /* rho_m c_pm / (rho_l c_pl) of the porous matrix */
+  double latent;                /* L_a */
+  double T_solidus, T_liquidus; /* T_s <= T_l (Eq. B8) */
+  double alpha_l, alpha_s;      /* effective diffusivities of each phase (Eq. B11, Sec. 4.3) */
+  double zeta_e, zeta_nu;       /* rates of the non-conserved moments 4-6 (Eq. 38) */
+  int32_t heat[6];              /* per face: 0 periodic, 1 adiabatic, 2 isothermal at T_wall */
+  double T_wall[6];
+  double T_init;                /* uniform initial temperature */
+} ref_enthalpy_params;
+
+typedef struct ref_enthalpy ref_enthalpy;
+int ref_enthalpy_create(const ref_enthalpy_params* p, ref_enthalpy** out);
+void ref_enthalpy_destroy(ref_enthalpy* h);
+int64_t ref_enthalpy_time(const ref_enthalpy* h);
+int ref_enthalpy_step(ref_enthalpy* h, int64_t nsteps);
+/* T, En, f_l per node (any pointer may be NULL) */
+int ref_enthalpy_fields(const ref_enthalpy* h, double* T, double* En, double* fl);
+/* g in [7][z][y][x] */
+int ref_enthalpy_get_state(const ref_enthalpy* h, double* g);
+int ref_enthalpy_set_state(ref_enthalpy* h, const double* g);
+/* T and f_l of an effective enthalpy (Eqs. B8, B9) */
+int ref_enthalpy_phase(const ref_enthalpy* h, double En, double* T, double* fl);
+
 #ifdef __cplusplus
 }
 #endif
