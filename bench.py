@@ -30,8 +30,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (D3Q19+D3Q7) & % HBM roofline; batched-solve p50/p99 latency"
 PEAK_HBM_GBPS = 8000.0
+# everything the step kernel is compiled from, build flags included
 KERNEL_SOURCES = ("paper_1611_03329_amd/csrc/kernels.hpp", "paper_1611_03329_amd/csrc/model.hpp",
-                  "paper_1611_03329_amd/csrc/lattice.hpp")
+                  "paper_1611_03329_amd/csrc/lattice.hpp", "paper_1611_03329_amd/csrc/batch.hpp",
+                  "paper_1611_03329_amd/build.py")
 
 
 def kernel_hash() -> str:
@@ -77,11 +79,11 @@ def _say(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def tune_launch(workloads, precision: str, interval: int, span: bool):
+def tune_launch(workloads, precision: str, interval: int):
     """Launch shape for a batch of these workloads, chosen by the batch
     autotuner on throw-away copies (the timed solves start fresh)."""
     from paper_1611_03329_amd import Batch, Lattice
-    b = Batch(interval, span=span)
+    b = Batch(interval)
     lats = [Lattice(w, precision) for w in workloads]
     for lat in lats:
         b.add(lat)
@@ -93,8 +95,8 @@ def tune_launch(workloads, precision: str, interval: int, span: bool):
 
 
 def bench_solves(args, kind: str) -> int:
-    """Solves to residual 1e-6: served (continuous batching, FP16 storage with
-    the FP32 finish) against one-after-another plain FP32 solves."""
+    """Solves to residual 1e-6, served with continuous batching (FP32, and FP16
+    storage with the FP32 finish) against one-after-another plain FP32 solves."""
     import torch
 
     import lbm_inputs
@@ -115,37 +117,43 @@ def bench_solves(args, kind: str) -> int:
         metric = "served-solve throughput and p50/p99 time-to-converge (residual 1e-6)"
     nodes = sum(q.workload["nx"] * q.workload["ny"] * q.workload["nz"] for q in reqs)
     _say(f"{kind}: {len(reqs)} requests, {nodes} nodes in all; tuning the launch shape")
-    shape = tune_launch([q.workload for q in reqs[:args.tune_count]], "fp16", args.fp16_interval, True)
+    shape = tune_launch([q.workload for q in reqs[:args.tune_count]], "fp32", 100)
     _say(f"launch shape (threads, blocks/CU, group bytes) = {shape}")
-    with Server("fp16", check_interval=100, tol=1e-6, max_steps=args.max_steps, hbm_budget=budget,
-                launch=shape, fp16_interval=args.fp16_interval) as srv:
-        served = srv.run(reqs, progress=_say)
-        stats = dict(srv.stats)
-    s_sum = summarize(served)
-    _say(f"served: {s_sum}")
+    runs = {}
+    for prec in ("fp32", "fp16"):
+        with Server(prec, check_interval=100, tol=1e-6, max_steps=args.max_steps, hbm_budget=budget,
+                    launch=shape) as srv:
+            res = srv.run(reqs, progress=_say)
+            stats = dict(srv.stats)
+        runs[prec] = (res, {**summarize(res), "promoted": stats["promoted"],
+                            "peak_members": stats["peak_members"], "peak_bytes": stats["peak_bytes"]})
+        _say(f"served {prec}: {runs[prec][1]}")
     seq = solve_sequential(reqs, "fp32", check_interval=100, tol=1e-6, max_steps=args.max_steps, progress=_say)
     q_sum = summarize(seq)
     _say(f"sequential fp32: {q_sum}")
-    dnu = [abs(a.nu[0] - b.nu[0]) / abs(b.nu[0]) for a, b in zip(served, seq) if a.nu and b.nu]
+
+    def nu_diff(res):
+        d = sorted(abs(a.nu[0] - b.nu[0]) / abs(b.nu[0]) for a, b in zip(res, seq) if a.nu and b.nu)
+        return {"max": d[-1] if d else None, "median": d[len(d) // 2] if d else None}
+
+    main_sum = runs["fp32"][1]
     line = {
         "metric": metric,
-        "value": round(s_sum["solves_per_s"], 4),
+        "value": round(main_sum["solves_per_s"], 4),
         "unit": "solves/s",
         "n_gpus": 1,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16 storage then f32 (f32 arithmetic)",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "requests": len(reqs), "nodes": nodes, "check_interval": 100,
-                   "fp16_interval": args.fp16_interval, "max_steps": args.max_steps, "launch": list(shape),
-                   "parallelism": "single GPU"},
-        "served": {**s_sum, "promoted": stats["promoted"], "peak_members": stats["peak_members"],
-                   "peak_bytes": stats["peak_bytes"]},
+                   "max_steps": args.max_steps, "launch": list(shape), "parallelism": "single GPU"},
+        "served_fp32": main_sum,
+        "served_fp16_then_fp32": runs["fp16"][1],
         "sequential_fp32": q_sum,
-        "speedup_solves_per_s": round(s_sum["solves_per_s"] / q_sum["solves_per_s"], 3),
-        "nu_hot_rel_diff_vs_sequential": {"max": max(dnu) if dnu else None,
-                                          "median": sorted(dnu)[len(dnu) // 2] if dnu else None},
+        "speedup_solves_per_s": {p: round(runs[p][1]["solves_per_s"] / q_sum["solves_per_s"], 3) for p in runs},
+        "nu_hot_rel_diff_vs_sequential": {p: nu_diff(runs[p][0]) for p in runs},
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -159,12 +167,11 @@ def main(argv=None) -> int:
     ap.add_argument("--rate", type=float, default=20.0, help="served: mean arrivals per second")
     ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="served: HBM budget for admission")
     ap.add_argument("--max-steps", type=int, default=100_000, help="solves: step cap per solve")
-    ap.add_argument("--fp16-interval", type=int, default=500, help="solves: FP16 residual interval")
     ap.add_argument("--tune-count", type=int, default=16, help="solves: workloads used to tune the launch shape")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--check-interval", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=3,
+    ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps on the 256^3 sample (0 skips the CPU baseline)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain device-to-device copy timed as the attainable-bandwidth "

@@ -54,6 +54,8 @@ extern "C" {
 typedef struct lbm_lattice lbm_lattice; /* opaque */
 typedef struct lbm_batch lbm_batch;     /* opaque */
 
+typedef enum { LBM_ENERGY_TEMPERATURE = 0, LBM_ENERGY_ENTHALPY = 1 } lbm_energy;
+
 typedef enum {
   LBM_OK = 0,
   LBM_ERR_INVALID_ARG = 1,   /* bad parameter, size or pointer */
@@ -127,6 +129,18 @@ typedef struct {
   double noise_amp;
   int32_t check_interval; /* K > 0: residual check at every multiple of K steps; 0 disables */
   double init_u[3];       /* initial velocity: f = f^eq(rho0, init_u), g = g^eq(T, init_u) */
+  /* ---- energy equation: LBM_ENERGY_TEMPERATURE (Sec. 3.2, default) or LBM_ENERGY_ENTHALPY
+   * (App. B: effective enthalpy with solid-liquid phase change, Eqs. B4-B13).  An enthalpy
+   * lattice carries only the D3Q7 populations and no flow (u = 0, the setting of the melting
+   * test of Sec. 4.3); it takes FP64 or FP32, periodic / adiabatic / isothermal faces,
+   * varpi, porosity, zeta_e, zeta_nu and the fields below, and check_interval 0. */
+  int32_t energy;
+  double c_pl, c_ps;      /* specific heats of the liquid and the solid (Eq. B2), > 0 */
+  double matrix_heat;     /* rho_m c_pm / (rho_l c_pl) of the porous matrix (Eq. B4), >= 0 */
+  double latent;          /* L_a >= 0 */
+  double T_solidus, T_liquidus;  /* T_s <= T_l (Eq. B8) */
+  double alpha_l, alpha_s;       /* effective diffusivity of each phase (Eq. B11), > 0 */
+  double T_init;          /* uniform initial temperature (g = g^eq of Eq. B12 at u = 0) */
 } lbm_params;
 
 /* Derived quantities (Eqs. 6, 7, 28, 32, 41, 51, 56). */
@@ -206,6 +220,19 @@ lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g);
  * counter is kept; the pending residual snapshot is discarded.  Asynchronous. */
 lbm_status lbm_set_state(lbm_lattice* h, const double* f, const double* g);
 
+/* Enthalpy lattices (energy = LBM_ENERGY_ENTHALPY): temperature (Eq. B8), effective
+ * enthalpy (Eq. B7) and liquid fraction (Eq. B9) at the current time into
+ * caller-owned DEVICE buffers of nx*ny*nz FP64 values, x fastest; any pointer may
+ * be NULL.  The heat capacity ratios of Eq. B4 are sigma_l = phi + (1 - phi)
+ * matrix_heat and sigma_s = phi c_ps / c_pl + (1 - phi) matrix_heat, c_p,ref is
+ * the harmonic mean of c_pl and c_ps (Eq. B13) and the liquidus enthalpy is
+ * sigma_l c_pl T_l + phi L_a.  Walls: anti-bounce-back at T_w with the weight
+ * varpi c_p,ref / 6 of Eq. B12, bounce-back at adiabatic walls.  Asynchronous.
+ * LBM_ERR_UNSUPPORTED for a temperature lattice; conversely lbm_fields,
+ * lbm_nusselt, lbm_totals, lbm_transfer_state and batches refuse enthalpy
+ * lattices, and their lbm_get_state / lbm_set_state take f = NULL. */
+lbm_status lbm_enthalpy_fields(lbm_lattice* h, double* T, double* En, double* fl);
+
 /* Copies the current pre-collision state of src into dst, converting the
  * storage precision (e.g. an FP16-storage lattice into an FP32 one).  Both must
  * have the same lattice type, shape and rest state (varpi, sigma, T_ref); the
@@ -268,23 +295,34 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
  * unstable.  Synchronizes. */
 lbm_status lbm_batch_residuals(lbm_batch* b, double* r, int64_t* at_step, int32_t* unstable, int32_t count);
 
-/* Launch shape: `block` threads per tile (64, 128 or 256; default 256); if
- * blocks_per_cu > 0 a persistent grid of blocks_per_cu blocks per compute unit
- * (at most the tile count) whose blocks walk the tile list, else (default) one
- * block per tile; and the group size limit group_bytes (0, the default: one
- * group per wall-rule set).  Whole check intervals run group by group, so a
+/* Launch shape of a batch. */
+typedef struct {
+  int32_t block;          /* threads per tile: 64, 128 or 256 (default 256) */
+  int32_t blocks_per_cu;  /* > 0: persistent grid of this many blocks per compute unit (at most
+                             the tile count) whose blocks walk the tile list; 0 (default): one
+                             block per tile */
+  uint64_t group_bytes;   /* group size limit (0, the default: one group per wall-rule set) */
+  int32_t xcd_ranges;     /* > 1: the tile list of a launch is cut into this many contiguous
+                             ranges, range r taken by the blocks the hardware places on XCD r
+                             (8 on MI355X), so neighbouring tiles share an L2; 0 (default):
+                             hardware order */
+} lbm_launch;
+
+/* Sets the launch shape.  Whole check intervals run group by group, so a
  * group whose populations fit the last-level cache is streamed from there.
  * Results do not depend on the launch shape except through the residual's
  * summation order, which follows `block`. */
-lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu, uint64_t group_bytes);
+lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu, uint64_t group_bytes,
+                                int32_t xcd_ranges);
 
 /* Chooses the launch shape by timing whole check intervals (HIP events, graph
- * replay off meanwhile): first group_bytes in {0, 32, 64, 128, 256, 512} MiB, then
- * block in {64, 128, 256}, then blocks_per_cu in {0, 4, 8}; each candidate
- * runs one untimed and one timed interval, after the batch first steps to the
- * start of an interval.  Writes the choice where the pointers are non-NULL and
- * keeps it.  The steps advance the members.  Synchronizes. */
-lbm_status lbm_batch_autotune(lbm_batch* b, int32_t* block, int32_t* blocks_per_cu, uint64_t* group_bytes);
+ * replay off meanwhile), one parameter at a time: group_bytes in {0, 8, 16,
+ * 32, 64, 128, 256, 512} MiB, then xcd_ranges in {0, 8}, then block in {64,
+ * 128, 256}, then blocks_per_cu in {0, 4, 8}; each candidate runs one untimed
+ * and one timed interval, after the batch first steps to the start of an
+ * interval.  Writes the choice to *out if non-NULL and keeps it.  The steps
+ * advance the members.  Synchronizes. */
+lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out);
 
 /* on != 0: the residual of a check compares with the state of K steps before
  * (r = max(|u(n) - u(n-K)|_2 / |u(n)|_2, |theta(n) - theta(n-K)|_2 /

@@ -13,6 +13,10 @@ ARCH = "gfx950"
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # fused multiply-adds only where one source expression has the form a * b + c:
+    # the rounding of every step is then the same in every kernel variant
+    # (check modes, batch or single lattice), whatever else the compiler sees
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
     # keep the compiler from forming packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

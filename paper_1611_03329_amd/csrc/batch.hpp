@@ -1,10 +1,12 @@
-// batch.hpp -- many lattices advanced by one launch per time step.
+// batch.hpp -- the step kernel over a table of lattices.
 //
-// Members of a batch share the lattice type, the storage precision and the
-// time parity (a lattice whose parity differs takes one step of its own before
-// it joins), so one launch of k_step_batch advances all of them by one step:
+// Every lattice is stepped through a member table: a single lattice is a table
+// of one; a batch's members share the lattice type, the storage precision and
+// the time parity (a lattice whose parity differs takes one step of its own
+// before it joins), so one launch of k_step advances all of them by one step:
 // tile t belongs to the member whose tile range holds t, and is processed by
-// the same per-block body as the single-lattice kernel on that member's state.  The
+// the per-block body step_block on that member's state.  One kernel for both
+// makes a member's trajectory bit for bit the same alone and in any batch.  The
 // residual check follows one schedule for the whole batch; per-member partials
 // are folded by k_fold_members into each member's result area and into one
 // batch-wide array that a single copy brings to the host.
@@ -38,17 +40,35 @@ __device__ __forceinline__ int member_of(const M* __restrict__ mem, int nmem, in
   return lo;
 }
 
-// One time step of every member.  Tile t (blockDim.x nodes of one member) is
-// taken by block t mod gridDim.x: with a grid smaller than the tile count the
-// blocks stay resident and walk the tile list (a persistent launch).
+// One time step of every member of a table: the step kernel of every lattice
+// (a single lattice is a table of one member).  Tile t (blockDim.x nodes of one
+// member) is taken by one block.  With nxcd > 1 the tile list is cut into nxcd
+// contiguous ranges and block b (which the hardware places on XCD b % nxcd)
+// walks range b % nxcd, so neighbouring tiles share an L2 cache; otherwise
+// block b takes tiles b, b + gridDim.x, ...  A grid smaller than the tile count
+// keeps its blocks resident and lets them walk several tiles (a persistent
+// launch).  With nxcd > 1 the grid is a multiple of nxcd.
 template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
-__global__ void __launch_bounds__(kMaxBlock) k_step_batch(const Member<S, C>* __restrict__ mem, int nmem,
-                                                          int ntiles) {
-  for (int t = (int)blockIdx.x; t < ntiles; t += (int)gridDim.x) {
+__global__ void __launch_bounds__(kMaxBlock) k_step(const Member<S, C>* __restrict__ mem, int nmem, int ntiles,
+                                                    int nxcd) {
+  int t, end, stride;
+  if (nxcd > 1) {
+    const int per = (ntiles + nxcd - 1) / nxcd;
+    const int x = (int)blockIdx.x % nxcd;
+    t = x * per + (int)blockIdx.x / nxcd;
+    end = min(ntiles, (x + 1) * per);
+    stride = (int)gridDim.x / nxcd;
+  } else {
+    t = (int)blockIdx.x;
+    end = ntiles;
+    stride = (int)gridDim.x;
+  }
+  for (; t < end; t += stride) {
     const int m = member_of(mem, nmem, t);
-    // private copies, as the single-lattice kernel receives them: the step's
-    // arithmetic then compiles exactly as there
-    const KParams<C> kp = mem[m].kp;
+    // the parameters are read in place: the general wall rules index their
+    // per-face arrays with a per-node face number, which a private copy would
+    // have to keep in scratch memory
+    const KParams<C>& kp = mem[m].kp;
     const S sto = mem[m].sto;
     C* const snap = mem[m].snap;
     double* const part = mem[m].part;

@@ -401,6 +401,54 @@ constexpr int kPartStride = 8;  // doubles per block in the partials buffer
 //   MODE 2 also accumulates, per block, sum|u - u_snap|^2, sum|u|^2,
 //   sum (theta - theta_snap)^2, sum theta^2 and max|u| into part[lb];
 //   MODE 3 does both: it compares with the snapshot, then replaces it.
+// The per-node body of a step: gather, moments, residual bookkeeping,
+// collisions, scatter.  G selects the general wall rules.
+template <class Lat, class S, class C, bool ODD, int MODE, bool G>
+__device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, C* __restrict__ snap, int n,
+                                          const Nbr& nb, double (&red)[5]) {
+  C h[Lat::Q], p[7];
+  gather<Lat, ODD, G, S, C>(kp, state, n, nb, h, p);
+  const Macro<C> M = macro<Lat, C>(kp, h, p);
+  LBM_GLOBAL C* sn = gbl(snap);
+  if constexpr (MODE == kModeCompare || MODE == kModeSpan) {
+    const double ux = M.ux, uy = M.uy, uz = M.uz, T = M.T;
+    const double dx = ux - (double)sn[n], dy = uy - (double)sn[n + kp.n], dz = uz - (double)sn[n + 2 * kp.n];
+    const double dT = (T - (double)sn[n + 3 * kp.n]) * (double)kp.inv_dT;
+    const double th = (T - (double)kp.T_ref) * (double)kp.inv_dT + 0.5;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    red[0] = dx * dx + dy * dy + dz * dz;
+    red[1] = uu;
+    red[2] = dT * dT;
+    red[3] = th * th;
+    red[4] = sqrt(uu);
+  }
+  if constexpr (MODE == kModeSnapshot || MODE == kModeSpan) {
+    sn[n] = M.ux;
+    sn[n + kp.n] = M.uy;
+    sn[n + 2 * kp.n] = M.uz;
+    sn[n + 3 * kp.n] = M.T;
+  }
+  collide_flow<Lat, C>(kp, M, h);
+  collide_heat<C>(kp, M, p);
+  scatter<Lat, ODD, G, S, C>(kp, state, n, nb, h, p, M);
+}
+
+// Node (x, y, z) lies on a face that moves or is open.
+template <class C>
+__device__ __forceinline__ bool on_special_face(const KParams<C>& kp, int x, int y, int z) {
+  const int s = kp.special;
+  return ((s & 1) && x == 0) || ((s & 2) && x == kp.nx - 1) || ((s & 4) && y == 0) ||
+         ((s & 8) && y == kp.ny - 1) || ((s & 16) && z == 0) || ((s & 32) && z == kp.nz - 1);
+}
+
+// One fused time step of the nodes of one block (block index lb of the lattice).
+//   MODE 1 also stores u and T of the pre-collision state into snap (4 planes of n);
+//   MODE 2 also accumulates, per block, sum|u - u_snap|^2, sum|u|^2,
+//   sum (theta - theta_snap)^2, sum theta^2 and max|u| into part[lb];
+//   MODE 3 does both: it compares with the snapshot, then replaces it.
+// With GEN the general wall rules run only in wavefronts that hold a node on a
+// moving or open face; every other wavefront takes the lean rules, which give
+// the same result for its nodes.  The choice is uniform per wavefront.
 template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
 __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state, C* __restrict__ snap,
                                            double* __restrict__ part, int lb) {
@@ -410,31 +458,14 @@ __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state,
     int x, y, z;
     node_coords(kp, n, x, y, z);
     const Nbr nb = make_nbr(kp, x, y, z);
-    C h[Lat::Q], p[7];
-    gather<Lat, ODD, GEN, S, C>(kp, state, n, nb, h, p);
-    const Macro<C> M = macro<Lat, C>(kp, h, p);
-    LBM_GLOBAL C* sn = gbl(snap);
-    if constexpr (MODE == kModeCompare || MODE == kModeSpan) {
-      const double ux = M.ux, uy = M.uy, uz = M.uz, T = M.T;
-      const double dx = ux - (double)sn[n], dy = uy - (double)sn[n + kp.n], dz = uz - (double)sn[n + 2 * kp.n];
-      const double dT = (T - (double)sn[n + 3 * kp.n]) * (double)kp.inv_dT;
-      const double th = (T - (double)kp.T_ref) * (double)kp.inv_dT + 0.5;
-      const double uu = ux * ux + uy * uy + uz * uz;
-      red[0] = dx * dx + dy * dy + dz * dz;
-      red[1] = uu;
-      red[2] = dT * dT;
-      red[3] = th * th;
-      red[4] = sqrt(uu);
+    if constexpr (GEN) {
+      if (__ballot(on_special_face(kp, x, y, z)) != 0)
+        step_node<Lat, S, C, ODD, MODE, true>(kp, state, snap, n, nb, red);
+      else
+        step_node<Lat, S, C, ODD, MODE, false>(kp, state, snap, n, nb, red);
+    } else {
+      step_node<Lat, S, C, ODD, MODE, false>(kp, state, snap, n, nb, red);
     }
-    if constexpr (MODE == kModeSnapshot || MODE == kModeSpan) {
-      sn[n] = M.ux;
-      sn[n + kp.n] = M.uy;
-      sn[n + 2 * kp.n] = M.uz;
-      sn[n + 3 * kp.n] = M.T;
-    }
-    collide_flow<Lat, C>(kp, M, h);
-    collide_heat<C>(kp, M, p);
-    scatter<Lat, ODD, GEN, S, C>(kp, state, n, nb, h, p, M);
   }
   if constexpr (MODE == kModeCompare || MODE == kModeSpan) {
     block_reduce<5>(red, 1u << 4);
@@ -444,13 +475,6 @@ __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state,
       for (int j = 0; j < 5; ++j) pt[(size_t)lb * kPartStride + j] = red[j];
     }
   }
-}
-
-// One fused time step for every node of one lattice.
-template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
-__global__ void __launch_bounds__(kMaxBlock) k_step(const KParams<C> kp, const S state,
-                                                    C* __restrict__ snap, double* __restrict__ part) {
-  step_block<Lat, S, C, ODD, MODE, GEN>(kp, state, snap, part, blockIdx.x);
 }
 
 // First stage of the two-stage reduction of per-block partials: block b folds

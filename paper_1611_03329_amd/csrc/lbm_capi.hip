@@ -13,6 +13,7 @@
 
 #include "lbm.h"
 #include "batch.hpp"
+#include "enthalpy.hpp"
 #include "kernels.hpp"
 
 #include <algorithm>
@@ -52,6 +53,7 @@ struct lbm_lattice {
   size_t bytes = 0;
   int q = 19;
   int prec = LBM_FP64;
+  int energy = LBM_ENERGY_TEMPERATURE;
   int nodes = 0;
   int pstride = 0;
   int block = 256;
@@ -65,6 +67,7 @@ struct lbm_lattice {
   double* part2 = nullptr;  // first-stage fold of part
   int nfold = 0;            // entries in part2
   double* res = nullptr;    // [0..7] residual, [8..13] wall flux, [16..17] totals
+  void* dev_member = nullptr; // the lattice as a one-member table for the step kernel
   int* dev_iso = nullptr;   // [6] isothermal flags
   double* dev_Tw = nullptr; // [6] wall temperatures
   double* host_res = nullptr; // pinned mirror of res (32 doubles)
@@ -120,14 +123,68 @@ extern "C" void lbm_default_params(lbm_params* p) {
     p->face[k].heat = LBM_HEAT_ADIABATIC;
   }
   p->check_interval = 0;
+  p->energy = LBM_ENERGY_TEMPERATURE;
+  p->c_pl = 1.0;
+  p->c_ps = 1.0;
+  p->alpha_l = 0.05;
+  p->alpha_s = 0.05;
 }
 
 static bool is_finite(double v) { return std::isfinite(v); }
+
+// Validation of an enthalpy lattice (App. B, conduction only).
+static lbm_status derive_enthalpy(const lbm_params* p, lbm_derived* d) {
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
+    return fail(LBM_ERR_UNSUPPORTED, "enthalpy lattices take FP64 or FP32 (precision %d)", p->precision);
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return fail(LBM_ERR_INVALID_ARG, "box %dx%dx%d must have at least one node per axis", p->nx, p->ny, p->nz);
+  const long long nodes = (long long)p->nx * p->ny * p->nz;
+  if (nodes > (1ll << 30) || 6ll * ((nodes + 127) / 128 * 128) * 8 >= (1ll << 32))
+    return fail(LBM_ERR_UNSUPPORTED, "box of %lld nodes is too large for one lattice", nodes);
+  if (!(p->porosity > 0.0 && p->porosity <= 1.0)) return fail(LBM_ERR_INVALID_ARG, "porosity must be in (0,1]");
+  if (!(p->varpi > 0.0 && p->varpi < 1.0)) return fail(LBM_ERR_INVALID_ARG, "varpi must be in (0,1)");
+  if (!(p->c_pl > 0.0) || !(p->c_ps > 0.0) || !is_finite(p->c_pl) || !is_finite(p->c_ps))
+    return fail(LBM_ERR_INVALID_ARG, "c_pl and c_ps must be > 0");
+  if (!(p->matrix_heat >= 0.0) || !is_finite(p->matrix_heat))
+    return fail(LBM_ERR_INVALID_ARG, "matrix_heat must be >= 0");
+  if (!(p->latent >= 0.0) || !is_finite(p->latent)) return fail(LBM_ERR_INVALID_ARG, "latent must be >= 0");
+  if (!(p->T_liquidus >= p->T_solidus) || !is_finite(p->T_liquidus) || !is_finite(p->T_solidus))
+    return fail(LBM_ERR_INVALID_ARG, "T_liquidus must be >= T_solidus");
+  if (!(p->alpha_l > 0.0) || !(p->alpha_s > 0.0) || !is_finite(p->alpha_l) || !is_finite(p->alpha_s))
+    return fail(LBM_ERR_INVALID_ARG, "alpha_l and alpha_s must be > 0");
+  if (!(p->zeta_e > 0.0 && p->zeta_e < 2.0) || !(p->zeta_nu > 0.0 && p->zeta_nu < 2.0))
+    return fail(LBM_ERR_INVALID_ARG, "zeta_e and zeta_nu must be in (0,2)");
+  if (!is_finite(p->T_init)) return fail(LBM_ERR_INVALID_ARG, "T_init must be finite");
+  if (p->check_interval != 0)
+    return fail(LBM_ERR_UNSUPPORTED, "enthalpy lattices have no residual check (check_interval must be 0)");
+  for (int a = 0; a < 3; ++a) {
+    const lbm_face& lo = p->face[2 * a];
+    const lbm_face& hi = p->face[2 * a + 1];
+    for (const lbm_face* f : {&lo, &hi}) {
+      if (f->heat != LBM_HEAT_PERIODIC && f->heat != LBM_HEAT_ADIABATIC && f->heat != LBM_HEAT_ISOTHERMAL)
+        return fail(LBM_ERR_UNSUPPORTED, "enthalpy lattices take periodic, adiabatic or isothermal faces");
+      if ((f->flow == LBM_FLOW_PERIODIC) != (f->heat == LBM_HEAT_PERIODIC))
+        return fail(LBM_ERR_INVALID_ARG, "a face must be periodic for both flow and heat, or for neither");
+      if (!is_finite(f->T_wall)) return fail(LBM_ERR_INVALID_ARG, "wall temperature must be finite");
+    }
+    if ((lo.heat == LBM_HEAT_PERIODIC) != (hi.heat == LBM_HEAT_PERIODIC))
+      return fail(LBM_ERR_INVALID_ARG, "opposite faces of axis %d must both be periodic or both not", a);
+  }
+  std::memset(d, 0, sizeof(*d));
+  const int dims[3] = {p->nx, p->ny, p->nz};
+  d->L = dims[(p->length_axis >= 0 && p->length_axis <= 2) ? p->length_axis : 0];
+  d->alpha_e = p->alpha_s;
+  d->alpha = p->alpha_s;
+  d->zeta_alpha = 1.0 / (0.5 + p->alpha_s * 3.0 / p->varpi);  // Eq. B11, solid phase
+  return LBM_OK;
+}
 
 // Validation and the parameter mapping of Sec. 4: Eq. 56 for a cavity (Ra, Pr, Ma),
 // Eq. 51 read with 1/s_nu for a channel (Re, u_char), then Eqs. 32, 41, 7, 6, 28.
 static lbm_status derive(const lbm_params* p, lbm_derived* d) {
   if (!p || !d) return fail(LBM_ERR_INVALID_ARG, "null parameter pointer");
+  if (p->energy == LBM_ENERGY_ENTHALPY) return derive_enthalpy(p, d);
+  if (p->energy != LBM_ENERGY_TEMPERATURE) return fail(LBM_ERR_UNSUPPORTED, "energy model %d", p->energy);
   if (p->lattice != 19 && p->lattice != 15)
     return fail(LBM_ERR_INVALID_ARG, "lattice must be 19 or 15 (got %d)", p->lattice);
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32 && p->precision != LBM_FP16_STORAGE)
@@ -227,6 +284,7 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
   k->moving = 0;
   k->open_flow = 0;
   k->open_heat = 0;
+  k->special = 0;
   for (int a = 0; a < 3; ++a) k->per[a] = p->face[2 * a].flow == LBM_FLOW_PERIODIC;
   const double w7 = p->varpi / 6.0;
   for (int f = 0; f < 6; ++f) {
@@ -234,13 +292,18 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
       const double u = p->face[f].flow == LBM_FLOW_WALL ? p->face[f].u_wall[a] : 0.0;
       k->u_wall[f][a] = (C)u;
       if (u != 0.0) k->moving = 1;
+      if (u != 0.0) k->special |= 1 << f;
     }
     if (p->face[f].flow == LBM_FLOW_OUTLET) k->open_flow |= 1 << f;
     if (p->face[f].heat == LBM_HEAT_OUTFLOW) k->open_heat |= 1 << f;
+    if (p->face[f].flow == LBM_FLOW_OUTLET || p->face[f].heat == LBM_HEAT_OUTFLOW) k->special |= 1 << f;
     if (p->face[f].heat == LBM_HEAT_ISOTHERMAL) {
-      // shifted anti-bounce-back: p_in = -p_out + 2 omega sigma (T_w - T_ref)
+      // shifted anti-bounce-back: p_in = -p_out + 2 omega sigma (T_w - T_ref); for
+      // the (unshifted) enthalpy populations the weight is varpi c_p,ref / 6 (Eq. B12)
       k->heat_a[f] = (C)-1.0;
-      k->heat_b[f] = (C)(2.0 * w7 * p->sigma * (p->face[f].T_wall - p->T_ref));
+      k->heat_b[f] = p->energy == LBM_ENERGY_ENTHALPY
+                         ? (C)(2.0 * w7 * (2.0 / (1.0 / p->c_pl + 1.0 / p->c_ps)) * p->face[f].T_wall)
+                         : (C)(2.0 * w7 * p->sigma * (p->face[f].T_wall - p->T_ref));
     } else {
       k->heat_a[f] = (C)1.0;
       k->heat_b[f] = (C)0.0;
@@ -280,8 +343,40 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
 
 // Device layout: [moving f | moving g | rest f, g | snapshot | partials |
 // folded partials | results | flags], every region 256-byte aligned.
+// Constants of the enthalpy model: Eq. B4 with rho_l = rho_s = rho0 and the
+// matrix as r_m = rho_m c_pm / (rho_l c_pl); c_p,ref the harmonic mean of c_pl
+// and c_ps (Eq. B13); En_l = sigma_l c_pl T_l + phi L_a (Eq. B8).
+template <class C>
+static EnthalpyConsts<C> enthalpy_consts(const lbm_params* p) {
+  const double sig_l = p->porosity + (1.0 - p->porosity) * p->matrix_heat;
+  const double sig_s = p->porosity * p->c_ps / p->c_pl + (1.0 - p->porosity) * p->matrix_heat;
+  const double cpref = 2.0 / (1.0 / p->c_pl + 1.0 / p->c_ps);
+  const double En_s = sig_s * p->c_pl * p->T_solidus;
+  const double En_l = sig_l * p->c_pl * p->T_liquidus + p->porosity * p->latent;
+  EnthalpyConsts<C> e;
+  e.varpi_cpref = (C)(p->varpi * cpref);
+  e.inv_sig_s_cpl = (C)(1.0 / (sig_s * p->c_pl));
+  e.inv_sig_l_cpl = (C)(1.0 / (sig_l * p->c_pl));
+  e.En_s = (C)En_s;
+  e.En_l = (C)En_l;
+  e.inv_dEn = En_l > En_s ? (C)(1.0 / (En_l - En_s)) : (C)0;
+  e.T_s = (C)p->T_solidus;
+  e.T_l = (C)p->T_liquidus;
+  e.alpha_l = (C)p->alpha_l;
+  e.alpha_s = (C)p->alpha_s;
+  e.inv_csT2 = (C)(3.0 / p->varpi);
+  e.zeta_e = (C)p->zeta_e;
+  e.zeta_nu = (C)p->zeta_nu;
+  return e;
+}
+
+// device bytes reserved for the lattice's one-member table
+constexpr size_t kMemberBytes = 2048;
+static_assert(sizeof(Member<Store<double, double, double>, double>) <= kMemberBytes, "member table entry too large");
+static_assert(sizeof(Member<Store<float, float, float>, float>) <= kMemberBytes, "member table entry too large");
+
 struct Layout {
-  size_t mf, mg, rs, snap, part, part2, res, iso, Tw, total;
+  size_t mf, mg, rs, snap, part, part2, res, iso, Tw, member, total;
   int pstride, nblocks, block, nfold;
 };
 
@@ -295,14 +390,15 @@ static Layout layout(const lbm_params* p) {
   // population planes start on 256-byte boundaries
   L.pstride = (int)align_up((size_t)nodes, 128);
   size_t off = 0;
+  const bool enth = p->energy == LBM_ENERGY_ENTHALPY;  // no flow populations, no check snapshot
   L.mf = off;
-  off += align_up((size_t)(p->lattice - 1) * L.pstride * s, 256);
+  off += enth ? 0 : align_up((size_t)(p->lattice - 1) * L.pstride * s, 256);
   L.mg = off;
   off += align_up((size_t)6 * L.pstride * c, 256);
   L.rs = off;
   off += align_up((size_t)2 * L.pstride * c, 256);
   L.snap = off;
-  off += align_up((size_t)4 * nodes * c, 256);
+  off += enth ? 0 : align_up((size_t)4 * nodes * c, 256);
   L.part = off;
   // sized for the smallest block a batch may use (64 threads)
   off += align_up((size_t)((nodes + 63) / 64) * kPartStride * sizeof(double), 256);
@@ -315,6 +411,8 @@ static Layout layout(const lbm_params* p) {
   off += 256;
   L.Tw = off;
   off += 256;
+  L.member = off;
+  off += kMemberBytes;
   L.total = off;
   return L;
 }
@@ -382,6 +480,7 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   h->stream = (hipStream_t)stream;
   h->q = p->lattice;
   h->prec = p->precision;
+  h->energy = p->energy;
   h->nodes = p->nx * p->ny * p->nz;
   h->pstride = L.pstride;
   h->block = L.block;
@@ -416,6 +515,7 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   h->res = reinterpret_cast<double*>(base + L.res);
   h->dev_iso = reinterpret_cast<int*>(base + L.iso);
   h->dev_Tw = reinterpret_cast<double*>(base + L.Tw);
+  h->dev_member = base + L.member;
   fill_kparams<double>(p, &d, h->nodes, h->pstride, &h->kd);
   fill_kparams<float>(p, &d, h->nodes, h->pstride, &h->kf);
 
@@ -431,7 +531,27 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
     if (h->owns_buf) (void)hipFree(h->buf);
     delete h;
   };
+  // the one-member table of the step kernel (check = 1: the host launches a
+  // compare step only when its snapshot is valid)
+  alignas(16) unsigned char table[kMemberBytes];
+  std::memset(table, 0, sizeof table);
+  if (!h->energy) with_types(h, [&](auto, auto s_t, auto c_t, const auto& kp) {
+    using S = decltype(s_t);
+    using C = decltype(c_t);
+    Member<S, C> m;
+    std::memset(&m, 0, sizeof m);
+    m.kp = kp;
+    m.sto = make_store<S>(h);
+    m.snap = static_cast<C*>(h->snap);
+    m.part = h->part;
+    m.res = h->res;
+    m.block0 = 0;
+    m.nblocks = h->nblocks;
+    m.check = 1;
+    std::memcpy(table, &m, sizeof m);
+  });
   if (hipMemsetAsync(h->res, 0, 256, h->stream) != hipSuccess ||
+      hipMemcpyAsync(h->dev_member, table, sizeof table, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
       hipMemcpyAsync(h->dev_iso, iso, sizeof iso, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
       hipMemcpyAsync(h->dev_Tw, Tw, sizeof Tw, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
     cleanup();
@@ -439,13 +559,30 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   }
   InitArgs ia{p->init_axis, p->init_T_lo, p->init_T_hi, p->seed, p->noise_amp,
               {p->init_u[0], p->init_u[1], p->init_u[2]}};
-  with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
-    using Lat = decltype(lat);
-    using S = decltype(s_t);
-    using C = decltype(c_t);
-    hipLaunchKernelGGL((k_init<Lat, S, C>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, ia,
-                       make_store<S>(h));
-  });
+  if (h->energy) {
+    // g = g^eq(En0, T0) of Eq. B12 at u = 0, En0 from T_init (Eq. B8 inverted)
+    const EnthalpyConsts<double> ec = enthalpy_consts<double>(p);
+    const double T0 = p->T_init;
+    double En0;
+    if (T0 <= p->T_solidus) En0 = T0 / ec.inv_sig_s_cpl;
+    else if (T0 >= p->T_liquidus) En0 = ec.En_l + (T0 - p->T_liquidus) / ec.inv_sig_l_cpl;
+    else En0 = ec.En_s + (T0 - p->T_solidus) / (p->T_liquidus - p->T_solidus) * (ec.En_l - ec.En_s);
+    const double g0 = En0 - ec.varpi_cpref * T0, gk = ec.varpi_cpref * T0 / 6.0;
+    if (h->prec == LBM_FP64)
+      hipLaunchKernelGGL((k_init_enthalpy<Store<double, double, double>, double>), dim3(h->nblocks),
+                         dim3(h->block), 0, h->stream, h->kd, make_store<Store<double, double, double>>(h), g0, gk);
+    else
+      hipLaunchKernelGGL((k_init_enthalpy<Store<float, float, float>, float>), dim3(h->nblocks), dim3(h->block),
+                         0, h->stream, h->kf, make_store<Store<float, float, float>>(h), g0, gk);
+  } else {
+    with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
+      using Lat = decltype(lat);
+      using S = decltype(s_t);
+      using C = decltype(c_t);
+      hipLaunchKernelGGL((k_init<Lat, S, C>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, ia,
+                         make_store<S>(h));
+    });
+  }
   st_ = launch_check("init");
   if (st_ != LBM_OK) {
     cleanup();
@@ -493,15 +630,14 @@ extern "C" lbm_status lbm_derived_params(const lbm_lattice* h, lbm_derived* d) {
 // ------------------------------------------------------------------ step
 template <class Lat, class S, class C, bool ODD, bool GEN>
 static void launch_step_mode(lbm_lattice* h, const KParams<C>& kp, int mode) {
-  const S st_ = make_store<S>(h);
-  C* sn = static_cast<C*>(h->snap);
+  const auto* mem = static_cast<const Member<S, C>*>(h->dev_member);
   const dim3 g(h->nblocks), b(h->block);
   if (mode == kModePlain)
-    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModePlain, GEN>), g, b, 0, h->stream, kp, st_, sn, h->part);
+    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModePlain, GEN>), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
   else if (mode == kModeSnapshot)
-    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModeSnapshot, GEN>), g, b, 0, h->stream, kp, st_, sn, h->part);
+    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModeSnapshot, GEN>), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
   else
-    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModeCompare, GEN>), g, b, 0, h->stream, kp, st_, sn, h->part);
+    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModeCompare, GEN>), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
 }
 
 // GEN (moving walls or open faces present) selects the kernels that compile
@@ -523,6 +659,27 @@ extern "C" lbm_status lbm_step(lbm_lattice* h, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_ERR_INVALID_ARG, "nsteps must be >= 0");
   if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice is in a batch: step the batch");
   if (h->host_res[7] != 0.0) return fail(LBM_ERR_UNSTABLE, "lattice was found unstable at an earlier check");
+  if (h->energy) {
+    const EnthalpyConsts<double> e64 = enthalpy_consts<double>(&h->p);
+    const EnthalpyConsts<float> e32 = enthalpy_consts<float>(&h->p);
+    using S64 = Store<double, double, double>;
+    using S32 = Store<float, float, float>;
+    for (int64_t s = 0; s < nsteps; ++s) {
+      const dim3 g(h->nblocks), b(h->block);
+      if (h->prec == LBM_FP64) {
+        if (h->parity) hipLaunchKernelGGL((k_step_enthalpy<S64, double, true>), g, b, 0, h->stream, h->kd, e64, make_store<S64>(h));
+        else hipLaunchKernelGGL((k_step_enthalpy<S64, double, false>), g, b, 0, h->stream, h->kd, e64, make_store<S64>(h));
+      } else {
+        if (h->parity) hipLaunchKernelGGL((k_step_enthalpy<S32, float, true>), g, b, 0, h->stream, h->kf, e32, make_store<S32>(h));
+        else hipLaunchKernelGGL((k_step_enthalpy<S32, float, false>), g, b, 0, h->stream, h->kf, e32, make_store<S32>(h));
+      }
+      lbm_status ls = launch_check("enthalpy step");
+      if (ls != LBM_OK) return ls;
+      h->parity ^= 1;
+      h->t += 1;
+    }
+    return LBM_OK;
+  }
   const int64_t K = h->p.check_interval;
   for (int64_t s = 0; s < nsteps; ++s) {
     int mode = kModePlain;
@@ -559,6 +716,7 @@ extern "C" lbm_status lbm_step(lbm_lattice* h, int64_t nsteps) {
 // ------------------------------------------------------------------ queries
 extern "C" lbm_status lbm_fields(lbm_lattice* h, double* rho, double* ux, double* uy, double* uz, double* T) {
   if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
+  if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_fields (use lbm_enthalpy_fields) is not available for enthalpy lattices");
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
@@ -574,6 +732,7 @@ extern "C" lbm_status lbm_fields(lbm_lattice* h, double* rho, double* ux, double
 
 extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {
   if (!h || !nu) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_nusselt is not available for enthalpy lattices");
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
@@ -619,6 +778,7 @@ extern "C" lbm_status lbm_residual(lbm_lattice* h, double* r, int64_t* at_step) 
 
 extern "C" lbm_status lbm_totals(lbm_lattice* h, double* mass, double* heat) {
   if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
+  if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_totals is not available for enthalpy lattices");
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
@@ -646,6 +806,20 @@ extern "C" lbm_status lbm_totals(lbm_lattice* h, double* mass, double* heat) {
 
 extern "C" lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g) {
   if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
+  if (h->energy) {
+    if (f) return fail(LBM_ERR_INVALID_ARG, "an enthalpy lattice has no flow populations (f must be NULL)");
+    if (!g) return LBM_OK;
+    if (h->prec == LBM_FP64) {
+      using S = Store<double, double, double>;
+      if (h->parity) hipLaunchKernelGGL((k_get_g<S, double, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, make_store<S>(h), g);
+      else hipLaunchKernelGGL((k_get_g<S, double, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, make_store<S>(h), g);
+    } else {
+      using S = Store<float, float, float>;
+      if (h->parity) hipLaunchKernelGGL((k_get_g<S, float, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, make_store<S>(h), g);
+      else hipLaunchKernelGGL((k_get_g<S, float, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, make_store<S>(h), g);
+    }
+    return launch_check("get_state");
+  }
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
@@ -660,6 +834,20 @@ extern "C" lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g) {
 }
 
 extern "C" lbm_status lbm_set_state(lbm_lattice* h, const double* f, const double* g) {
+  if (h && h->energy) {
+    if (f || !g) return fail(LBM_ERR_INVALID_ARG, "an enthalpy lattice takes g only (f must be NULL)");
+    if (h->prec == LBM_FP64) {
+      using S = Store<double, double, double>;
+      hipLaunchKernelGGL((k_set_g<S, double>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, make_store<S>(h), g);
+    } else {
+      using S = Store<float, float, float>;
+      hipLaunchKernelGGL((k_set_g<S, float>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, make_store<S>(h), g);
+    }
+    lbm_status ls = launch_check("set_state");
+    if (ls != LBM_OK) return ls;
+    h->parity = 0;
+    return LBM_OK;
+  }
   if (!h || !f || !g) return fail(LBM_ERR_INVALID_ARG, "lbm_set_state needs both f and g");
   if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice is in a batch: remove it first");
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
@@ -676,9 +864,27 @@ extern "C" lbm_status lbm_set_state(lbm_lattice* h, const double* f, const doubl
   return LBM_OK;
 }
 
+extern "C" lbm_status lbm_enthalpy_fields(lbm_lattice* h, double* T, double* En, double* fl) {
+  if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
+  if (!h->energy) return fail(LBM_ERR_UNSUPPORTED, "not an enthalpy lattice (use lbm_fields)");
+  if (h->prec == LBM_FP64) {
+    using S = Store<double, double, double>;
+    const EnthalpyConsts<double> ec = enthalpy_consts<double>(&h->p);
+    if (h->parity) hipLaunchKernelGGL((k_fields_enthalpy<S, double, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, ec, make_store<S>(h), T, En, fl);
+    else hipLaunchKernelGGL((k_fields_enthalpy<S, double, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, ec, make_store<S>(h), T, En, fl);
+  } else {
+    using S = Store<float, float, float>;
+    const EnthalpyConsts<float> ec = enthalpy_consts<float>(&h->p);
+    if (h->parity) hipLaunchKernelGGL((k_fields_enthalpy<S, float, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, ec, make_store<S>(h), T, En, fl);
+    else hipLaunchKernelGGL((k_fields_enthalpy<S, float, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, ec, make_store<S>(h), T, En, fl);
+  }
+  return launch_check("enthalpy fields");
+}
+
 extern "C" lbm_status lbm_transfer_state(lbm_lattice* dst, lbm_lattice* src) {
   if (!dst || !src) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
   if (dst == src) return fail(LBM_ERR_INVALID_ARG, "source and destination are the same lattice");
+  if (dst->energy || src->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_transfer_state is not available for enthalpy lattices");
   if (dst->batch) return fail(LBM_ERR_INVALID_ARG, "the destination is in a batch: remove it first");
   if (dst->q != src->q || dst->p.nx != src->p.nx || dst->p.ny != src->p.ny || dst->p.nz != src->p.nz)
     return fail(LBM_ERR_INVALID_ARG, "source and destination differ in lattice type or shape");
@@ -738,6 +944,7 @@ struct lbm_batch {
   int per_cu = 0;            // resident blocks per compute unit (persistent launch); 0: one block per tile
   int ncu = 0;               // compute units of the device
   uint64_t group_bytes = 0;  // group size limit; 0: one group per wall-rule set
+  int nxcd = 0;              // > 1: contiguous tile ranges per XCD (that many XCDs)
   int64_t s = 0;
   int parity = 0;
   bool use_graph = false;
@@ -778,6 +985,12 @@ static uint64_t member_state_bytes(const lbm_lattice* h) {
 }
 
 static int batch_grid(const lbm_batch* b, int tiles) {
+  if (b->nxcd > 1) {
+    const int full = b->nxcd * ((tiles + b->nxcd - 1) / b->nxcd);
+    if (b->per_cu <= 0) return full;
+    const int resident = std::max(b->nxcd, (b->per_cu * std::max(b->ncu, 1)) / b->nxcd * b->nxcd);
+    return std::min(full, resident);
+  }
   return b->per_cu > 0 ? std::min(tiles, b->per_cu * std::max(b->ncu, 1)) : tiles;
 }
 
@@ -883,7 +1096,7 @@ static lbm_status batch_upload_typed(lbm_batch* b) {
   // captured launches read the member table from device memory: they stay
   // valid while the buffers, the groups and the launch shape are unchanged
   std::vector<int64_t> k = {(int64_t)(uintptr_t)b->dev_mem, (int64_t)(uintptr_t)b->dev_out,
-                            (int64_t)(uintptr_t)b->host_out, b->block, b->per_cu, b->check};
+                            (int64_t)(uintptr_t)b->host_out, b->block, b->per_cu, b->check, b->nxcd};
   for (const auto& g : b->groups) k.insert(k.end(), {g.gen, g.first, g.count, g.tiles});
   if (k != b->key) batch_drop_graphs(b);
   b->key = k;
@@ -926,11 +1139,11 @@ static void batch_launch_mode(const lbm_batch* b, const lbm_batch::Group& g) {
   const auto* mem = static_cast<const Member<S, C>*>(b->dev_mem) + g.first;
   const int grid = batch_grid(b, g.tiles);
   if (g.gen)
-    hipLaunchKernelGGL((k_step_batch<Lat, S, C, ODD, MODE, true>), dim3(grid), dim3(b->block), 0, b->stream, mem,
-                       g.count, g.tiles);
+    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, MODE, true>), dim3(grid), dim3(b->block), 0, b->stream, mem, g.count,
+                       g.tiles, b->nxcd);
   else
-    hipLaunchKernelGGL((k_step_batch<Lat, S, C, ODD, MODE, false>), dim3(grid), dim3(b->block), 0, b->stream, mem,
-                       g.count, g.tiles);
+    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, MODE, false>), dim3(grid), dim3(b->block), 0, b->stream, mem, g.count,
+                       g.tiles, b->nxcd);
 }
 
 // One step of group g: mode and parity as given.
@@ -1057,6 +1270,7 @@ extern "C" lbm_status lbm_batch_destroy(lbm_batch* b) {
 extern "C" lbm_status lbm_batch_add(lbm_batch* b, lbm_lattice* h) {
   if (!b || !h) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
   if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice already belongs to a batch");
+  if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "enthalpy lattices cannot join a batch");
   if (!b->members.empty() && (h->q != b->q || h->prec != b->prec))
     return fail(LBM_ERR_UNSUPPORTED, "batch members must share the lattice type and precision");
   if (h->stream != b->stream) {
@@ -1118,22 +1332,27 @@ extern "C" lbm_status lbm_batch_member(const lbm_batch* b, int32_t index, lbm_la
   return LBM_OK;
 }
 
-extern "C" lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu, uint64_t group_bytes) {
+extern "C" lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_cu, uint64_t group_bytes,
+                                           int32_t xcd_ranges) {
   if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
   if (block != 64 && block != 128 && block != 256)
     return fail(LBM_ERR_INVALID_ARG, "block must be 64, 128 or 256 (got %d)", block);
   if (blocks_per_cu < 0 || blocks_per_cu > 64)
     return fail(LBM_ERR_INVALID_ARG, "blocks_per_cu must be in [0, 64] (got %d)", blocks_per_cu);
+  if (xcd_ranges < 0 || xcd_ranges > 64)
+    return fail(LBM_ERR_INVALID_ARG, "xcd_ranges must be in [0, 64] (got %d)", xcd_ranges);
   if (blocks_per_cu > 0 && b->ncu == 0) {
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     b->ncu = ncu;
   }
-  if (block != b->block || blocks_per_cu != b->per_cu || group_bytes != b->group_bytes) {
+  const int nxcd = xcd_ranges > 1 ? xcd_ranges : 0;
+  if (block != b->block || blocks_per_cu != b->per_cu || group_bytes != b->group_bytes || nxcd != b->nxcd) {
     b->block = block;
     b->per_cu = blocks_per_cu;
     b->group_bytes = group_bytes;
+    b->nxcd = nxcd;
     b->dirty = true;
   }
   return LBM_OK;
@@ -1214,12 +1433,13 @@ extern "C" lbm_status lbm_batch_residuals(lbm_batch* b, double* r, int64_t* at_s
   return LBM_OK;
 }
 
-// Chooses the launch shape by timing, one parameter at a time: first the group
-// size limit (from none up to 512 MiB), then the threads per tile, then the
-// persistent grid.  Each candidate runs one untimed check interval (upload,
-// caches) and one timed by HIP events; with K = 0 single steps stand in for the
-// intervals.  The steps are real: the members advance.
-extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int32_t* block, int32_t* blocks_per_cu, uint64_t* group_bytes) {
+// Chooses the launch shape by timing, one parameter at a time: the group size
+// limit (none, 8 MiB ... 512 MiB), the tile order (hardware order, or one
+// contiguous range per XCD), the threads per tile, then the persistent grid.
+// Each candidate runs one untimed check interval (upload, caches) and one
+// timed by HIP events; with K = 0 single steps stand in for the intervals.
+// The steps are real: the members advance.
+extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
   if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
   if (b->members.empty()) return fail(LBM_ERR_INVALID_ARG, "the batch is empty");
   const int64_t K = b->check > 0 ? b->check : 1;
@@ -1234,10 +1454,9 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int32_t* block, int32_t* 
   }
   const bool graph = b->use_graph;
   b->use_graph = false;  // time the launches themselves
-  int cur[2] = {256, 0};  // threads per tile, blocks per CU
-  uint64_t gb = 0;
-  auto trial = [&](int bl, int pc, uint64_t g, float* ms) -> lbm_status {
-    lbm_status s2 = lbm_batch_set_launch(b, bl, pc, g);
+  lbm_launch cur{256, 0, 0, 0};
+  auto trial = [&](const lbm_launch& c, float* ms) -> lbm_status {
+    lbm_status s2 = lbm_batch_set_launch(b, c.block, c.blocks_per_cu, c.group_bytes, c.xcd_ranges);
     if (s2 == LBM_OK) s2 = lbm_batch_step(b, K);
     if (s2 != LBM_OK) return s2;
     if (b->dirty && (s2 = batch_upload(b)) != LBM_OK) return s2;
@@ -1249,35 +1468,45 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, int32_t* block, int32_t* 
     return LBM_OK;
   };
   const uint64_t MiB = 1ull << 20;
-  const uint64_t groups_c[6] = {0, 32 * MiB, 64 * MiB, 128 * MiB, 256 * MiB, 512 * MiB};
-  const int blocks_c[3] = {64, 128, 256};
-  const int per_cu_c[3] = {0, 4, 8};
+  const uint64_t groups_c[] = {0, 8 * MiB, 16 * MiB, 32 * MiB, 64 * MiB, 128 * MiB, 256 * MiB, 512 * MiB};
+  const int xcd_c[] = {0, 8};
+  const int blocks_c[] = {64, 128, 256};
+  const int per_cu_c[] = {0, 4, 8};
   float best = -1.0f, ms = 0.0f;
   for (uint64_t g : groups_c) {
-    if ((st_ = trial(cur[0], cur[1], g, &ms)) != LBM_OK) break;
-    if (best < 0.0f || ms < best) best = ms, gb = g;
+    lbm_launch c = cur;
+    c.group_bytes = g;
+    if ((st_ = trial(c, &ms)) != LBM_OK) break;
+    if (best < 0.0f || ms < best) best = ms, cur.group_bytes = g;
   }
-  const int start[2] = {cur[0], cur[1]};  // measured already
-  if (st_ == LBM_OK)
-    for (int bl : blocks_c) {
-      if (bl == start[0]) continue;
-      if ((st_ = trial(bl, cur[1], gb, &ms)) != LBM_OK) break;
-      if (ms < best) best = ms, cur[0] = bl;
-    }
-  if (st_ == LBM_OK)
-    for (int pc : per_cu_c) {
-      if (pc == start[1]) continue;
-      if ((st_ = trial(cur[0], pc, gb, &ms)) != LBM_OK) break;
-      if (ms < best) best = ms, cur[1] = pc;
-    }
+  const lbm_launch start = cur;  // measured already
+  for (int x : xcd_c) {
+    if (st_ != LBM_OK || x == start.xcd_ranges) continue;
+    lbm_launch c = cur;
+    c.xcd_ranges = x;
+    if ((st_ = trial(c, &ms)) != LBM_OK) break;
+    if (ms < best) best = ms, cur.xcd_ranges = x;
+  }
+  for (int bl : blocks_c) {
+    if (st_ != LBM_OK || bl == start.block) continue;
+    lbm_launch c = cur;
+    c.block = bl;
+    if ((st_ = trial(c, &ms)) != LBM_OK) break;
+    if (ms < best) best = ms, cur.block = bl;
+  }
+  for (int pc : per_cu_c) {
+    if (st_ != LBM_OK || pc == start.blocks_per_cu) continue;
+    lbm_launch c = cur;
+    c.blocks_per_cu = pc;
+    if ((st_ = trial(c, &ms)) != LBM_OK) break;
+    if (ms < best) best = ms, cur.blocks_per_cu = pc;
+  }
   b->use_graph = graph;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st_ != LBM_OK) return st_;
-  if (block) *block = cur[0];
-  if (blocks_per_cu) *blocks_per_cu = cur[1];
-  if (group_bytes) *group_bytes = gb;
-  return lbm_batch_set_launch(b, cur[0], cur[1], gb);
+  if (out) *out = cur;
+  return lbm_batch_set_launch(b, cur.block, cur.blocks_per_cu, cur.group_bytes, cur.xcd_ranges);
 }
 
 extern "C" const char* lbm_status_string(lbm_status s) {

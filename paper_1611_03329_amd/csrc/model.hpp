@@ -27,6 +27,7 @@ struct KParams {
   int moving;       // some wall face has a nonzero velocity (used when GEN)
   int open_flow;    // bit f set: face f is an open outlet for f (flow)
   int open_heat;    // bit f set: face f is an outflow face for g
+  int special;      // bit f set: face f moves or is open (its nodes need the general rules)
   C u_wall[6][3];   // wall velocity per face
   C heat_a[6];      // thermal wall rule: p_in = heat_a * p_out + heat_b (1, 0 on outflow faces)
   C heat_b[6];

@@ -26,6 +26,7 @@ FP64 = 0
 FP32 = 1
 FP16_STORAGE = 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_STORAGE}
+ENERGY = {"temperature": 0, "enthalpy": 1}
 FLOW = {"periodic": 0, "wall": 1, "outlet": 3}
 HEAT = {"periodic": 0, "adiabatic": 1, "isothermal": 2, "outflow": 3}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "device error",
@@ -71,7 +72,16 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
         ("check_interval", ctypes.c_int32),
         ("init_u", ctypes.c_double * 3),
+        ("energy", ctypes.c_int32),
+        ("c_pl", ctypes.c_double), ("c_ps", ctypes.c_double), ("matrix_heat", ctypes.c_double),
+        ("latent", ctypes.c_double), ("T_solidus", ctypes.c_double), ("T_liquidus", ctypes.c_double),
+        ("alpha_l", ctypes.c_double), ("alpha_s", ctypes.c_double), ("T_init", ctypes.c_double),
     ]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("group_bytes", ctypes.c_uint64),
+                ("xcd_ranges", ctypes.c_int32)]
 
 
 class Derived(ctypes.Structure):
@@ -95,6 +105,7 @@ _lib.lbm_step.argtypes = [_V, ctypes.c_int64]
 _lib.lbm_time.argtypes = [_V, _I64]
 _lib.lbm_derived_params.argtypes = [_V, ctypes.POINTER(Derived)]
 _lib.lbm_fields.argtypes = [_V, _V, _V, _V, _V, _V]
+_lib.lbm_enthalpy_fields.argtypes = [_V, _V, _V, _V]
 _lib.lbm_nusselt.argtypes = [_V, _D]
 _lib.lbm_residual.argtypes = [_V, _D, _I64]
 _lib.lbm_totals.argtypes = [_V, _D, _D]
@@ -113,14 +124,13 @@ _lib.lbm_batch_size.argtypes = [_V, ctypes.POINTER(ctypes.c_int32)]
 _lib.lbm_batch_member.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_V)]
 _lib.lbm_batch_step.argtypes = [_V, ctypes.c_int64]
 _lib.lbm_batch_residuals.argtypes = [_V, _D, _I64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
-_lib.lbm_batch_set_launch.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64]
-_lib.lbm_batch_autotune.argtypes = [_V, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                    ctypes.POINTER(ctypes.c_uint64)]
+_lib.lbm_batch_set_launch.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32]
+_lib.lbm_batch_autotune.argtypes = [_V, ctypes.POINTER(Launch)]
 _lib.lbm_batch_set_graph.argtypes = [_V, ctypes.c_int32]
 _lib.lbm_batch_set_span.argtypes = [_V, ctypes.c_int32]
 for _name in ("lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_step",
               "lbm_time", "lbm_derived_params", "lbm_fields", "lbm_nusselt", "lbm_residual",
-              "lbm_totals", "lbm_get_state", "lbm_set_state", "lbm_transfer_state", "lbm_batch_create", "lbm_batch_destroy",
+              "lbm_totals", "lbm_get_state", "lbm_set_state", "lbm_transfer_state", "lbm_enthalpy_fields", "lbm_batch_create", "lbm_batch_destroy",
               "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size", "lbm_batch_member", "lbm_batch_step",
               "lbm_batch_residuals", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_set_graph",
               "lbm_batch_set_span"):
@@ -159,6 +169,8 @@ def make_params(workload: dict, precision: str | int = "fp64", check_interval: i
                 arr[a] = float(val[a])
         elif key == "precision":
             continue
+        elif key == "energy":
+            p.energy = ENERGY[val] if isinstance(val, str) else int(val)
         elif key in _SKIP_KEYS:
             continue
         else:
@@ -193,7 +205,8 @@ class Lattice:
     def __init__(self, workload: dict, precision: str = "fp64", check_interval: int = 0,
                  stream: torch.cuda.Stream | None = None, device=None):
         self.params = make_params(workload, precision, check_interval)
-        self.q = int(self.params.lattice)
+        self.enthalpy = int(self.params.energy) == ENERGY["enthalpy"]
+        self.q = 0 if self.enthalpy else int(self.params.lattice)
         self.shape = (int(self.params.nz), int(self.params.ny), int(self.params.nx))
         self.nodes = self.shape[0] * self.shape[1] * self.shape[2]
         self.device = torch.device("cuda") if device is None else torch.device(device)
@@ -276,11 +289,20 @@ class Lattice:
         return float(m.value), float(q.value)
 
     def get_state(self):
-        f = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
+        """(f, g) pre-collision populations, FP64 device tensors; f is None for
+        an enthalpy lattice."""
+        f = None if self.enthalpy else torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
         g = torch.empty((7,) + self.shape, dtype=torch.float64, device=self.device)
         _check(_lib.lbm_get_state(self._h, _ptr(f), _ptr(g)))
         self._settle()
         return f, g
+
+    def enthalpy_fields(self) -> dict:
+        """T, En and f_l (Eqs. B7-B9) of an enthalpy lattice."""
+        out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device) for k in ("T", "En", "fl")}
+        _check(_lib.lbm_enthalpy_fields(self._h, _ptr(out["T"]), _ptr(out["En"]), _ptr(out["fl"])))
+        self._settle()
+        return out
 
     def transfer_from(self, other: "Lattice"):
         """Takes over the state of ``other`` (same lattice type, shape and rest
@@ -288,9 +310,12 @@ class Lattice:
         _check(_lib.lbm_transfer_state(self._h, other._h))
 
     def set_state(self, f, g):
-        f = torch.as_tensor(f, dtype=torch.float64).to(self.device).contiguous()
+        """Replaces the state (f must be None for an enthalpy lattice)."""
         g = torch.as_tensor(g, dtype=torch.float64).to(self.device).contiguous()
-        assert tuple(f.shape) == (self.q,) + self.shape and tuple(g.shape) == (7,) + self.shape
+        assert tuple(g.shape) == (7,) + self.shape
+        if f is not None:
+            f = torch.as_tensor(f, dtype=torch.float64).to(self.device).contiguous()
+            assert tuple(f.shape) == (self.q,) + self.shape
         _check(_lib.lbm_set_state(self._h, _ptr(f), _ptr(g)))
         # keep the inputs alive until the copy kernel has run
         self.stream.synchronize()
@@ -303,8 +328,8 @@ class Batch:
     graph, which needs a stream of its own: one is created when none is given."""
 
     def __init__(self, check_interval: int, stream: torch.cuda.Stream | None = None, graph: bool = False,
-                 block: int | None = None, per_cu: int = 0, group_bytes: int = 0, span: bool = False,
-                 device=None):
+                 block: int | None = None, per_cu: int = 0, group_bytes: int = 0, xcd_ranges: int = 0,
+                 span: bool = False, device=None):
         self.device = torch.device("cuda") if device is None else torch.device(device)
         if stream is None:
             stream = torch.cuda.Stream(self.device) if graph else torch.cuda.current_stream(self.device)
@@ -314,8 +339,8 @@ class Batch:
         _check(_lib.lbm_batch_create(ctypes.c_void_p(stream.cuda_stream), self.check_interval, ctypes.byref(h)))
         self._h = h
         self.members: list[Lattice] = []
-        if block is not None or per_cu or group_bytes:
-            self.set_launch(256 if block is None else block, per_cu, group_bytes)
+        if block is not None or per_cu or group_bytes or xcd_ranges:
+            self.set_launch(256 if block is None else block, per_cu, group_bytes, xcd_ranges)
         if graph:
             _check(_lib.lbm_batch_set_graph(self._h, 1))
         if span:
@@ -362,19 +387,18 @@ class Batch:
         """Residual over the whole check interval (True) or over one step."""
         _check(_lib.lbm_batch_set_span(self._h, int(bool(on))))
 
-    def set_launch(self, block: int, per_cu: int = 0, group_bytes: int = 0):
+    def set_launch(self, block: int, per_cu: int = 0, group_bytes: int = 0, xcd_ranges: int = 0):
         """Threads per tile, resident blocks per compute unit (0: one block per
-        tile) and the group size limit in bytes (0: no limit)."""
-        _check(_lib.lbm_batch_set_launch(self._h, int(block), int(per_cu), int(group_bytes)))
+        tile), the group size limit in bytes (0: no limit) and the number of
+        contiguous per-XCD tile ranges (0: hardware order)."""
+        _check(_lib.lbm_batch_set_launch(self._h, int(block), int(per_cu), int(group_bytes), int(xcd_ranges)))
 
     def autotune(self):
         """Times launch shapes over real check intervals; returns the chosen
-        (block, per_cu, group_bytes)."""
-        b = ctypes.c_int32()
-        c = ctypes.c_int32()
-        g = ctypes.c_uint64()
-        _check(_lib.lbm_batch_autotune(self._h, ctypes.byref(b), ctypes.byref(c), ctypes.byref(g)))
-        return int(b.value), int(c.value), int(g.value)
+        (block, per_cu, group_bytes, xcd_ranges)."""
+        c = Launch()
+        _check(_lib.lbm_batch_autotune(self._h, ctypes.byref(c)))
+        return int(c.block), int(c.blocks_per_cu), int(c.group_bytes), int(c.xcd_ranges)
 
     def residuals(self):
         """(r, at_step, unstable) lists in member order."""

@@ -91,37 +91,31 @@ class Server:
     precision "fp16": a solve starts in FP16 storage (136 instead of 208 bytes
     per node and step).  FP16 rounding of the stored populations puts a floor
     under the one-step residual (about 2e-4 to 7e-3 relative on the cavity
-    workloads), so the FP16 phase is watched with the residual over a whole
-    interval of `fp16_interval` steps (lbm_batch_set_span), whose rounding
-    floor divided by the interval is that many times lower.  When that
-    per-step rate falls below `promote_rate`, or stops falling (no new low by
-    the factor plateau[0] within plateau[1] checks), the solve moves to FP32
-    storage (lbm_transfer_state, exact) and finishes there with the one-step
-    residual.  The move is decided from the solve's own residuals at an
-    interval boundary, and the FP32 lattice starts its own check schedule at
-    time 0, so results stay independent of the mix.
+    workloads), reached within the first few thousand steps, after the fast
+    transient.  When the residual stops falling (no new low by the factor
+    plateau[0] within plateau[1] checks) the solve moves to FP32 storage
+    (lbm_transfer_state, exact) and finishes there.  Moving early matters: an
+    FP16 run kept going drifts towards the FP16 map's own fixed point, whose
+    distance from the FP32 one the FP32 finish then has to relax away.  The
+    move is decided from the solve's own residuals at a check boundary, and
+    the FP32 lattice starts its own check schedule at time 0, so results stay
+    independent of the mix.
 
-    Every batch advances `chunk` steps per round trip (the FP16 interval in
-    fp16 mode, else `check_interval`); admission and retirement happen between
-    chunks, where every batch's step counter is a multiple of its interval."""
+    Every batch advances `check_interval` steps per round trip; admission and
+    retirement happen between these chunks."""
 
-    def __init__(self, precision: str = "fp16", check_interval: int = 100, tol: float = 1e-6,
+    def __init__(self, precision: str = "fp32", check_interval: int = 100, tol: float = 1e-6,
                  max_steps: int = 200_000, hbm_budget: int | None = None, max_members: int = 256,
-                 graph: bool = True, launch: tuple | None = None, fp16_interval: int = 500,
-                 promote_rate: float = 1e-5, plateau: tuple = (0.9, 3), device=None):
+                 graph: bool = True, launch: tuple | None = None, plateau: tuple = (0.9, 5), device=None):
         if check_interval <= 0 or check_interval % 2:
             raise ValueError("check_interval must be a positive even number (chunks keep the parity)")
         if precision not in ("fp32", "fp16"):
             raise ValueError("precision must be fp32 or fp16")
-        if precision == "fp16" and fp16_interval % check_interval:
-            raise ValueError("fp16_interval must be a multiple of check_interval")
         self.precision = precision
         self.K = int(check_interval)
-        self.K16 = int(fp16_interval)
-        self.chunk = self.K16 if precision == "fp16" else self.K
+        self.chunk = self.K
         self.tol = float(tol)
         self.max_steps = int(max_steps)
-        self.promote_rate = float(promote_rate)
         self.plateau = (float(plateau[0]), int(plateau[1]))
         self.device = torch.device("cuda") if device is None else torch.device(device)
         if hbm_budget is None:
@@ -132,7 +126,7 @@ class Server:
         # one batch per storage precision, each on a stream of its own
         self.batches = {"fp32": Batch(self.K, graph=graph, device=self.device)}
         if precision == "fp16":
-            self.batches["fp16"] = Batch(self.K16, graph=graph, span=True, device=self.device)
+            self.batches["fp16"] = Batch(self.K, graph=graph, device=self.device)
         if launch is not None:
             for b in self.batches.values():
                 b.set_launch(*launch)
@@ -218,26 +212,17 @@ class Server:
                     e = active[id(lat)]
                     res = e["res"]
                     steps = e["base"] + lat.time
-                    if prec == "fp16":
-                        res.steps = steps
-                        if uu:
-                            res.unstable = True
-                        if uu or steps >= self.max_steps:
-                            b.remove(lat)
-                            retire(lat, e)
-                            continue
-                        if aa <= 0:
-                            continue
-                        rate = rr / self.K16
-                        if rate < e["best"] * self.plateau[0]:
-                            e["best"], e["since"] = rate, 0
-                        else:
-                            e["since"] += 1
-                        if rate < self.promote_rate or e["since"] >= self.plateau[1]:
-                            promote.append(lat)
-                    elif _done(res, rr, aa, uu, steps, self.tol, self.max_steps):
+                    if _done(res, rr, aa, uu, steps, self.tol, self.max_steps):
                         b.remove(lat)
                         retire(lat, e)
+                    elif prec == "fp16" and aa > 0:
+                        # the FP16 floor: no new low by the factor within the last checks
+                        if rr < e["best"] * self.plateau[0]:
+                            e["best"], e["since"] = rr, 0
+                        else:
+                            e["since"] += 1
+                        if e["since"] >= self.plateau[1]:
+                            promote.append(lat)
             for lat in promote:
                 e = active[id(lat)]
                 n32 = need[e["q"].rid]["fp32"]

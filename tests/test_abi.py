@@ -45,7 +45,9 @@ def test_ctypes_layout_matches_c_header():
     from paper_1611_03329_amd import lbm
     fields = [f for f, _ in lbm.Params._fields_]
     prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "lbm.h"', "int main(void){",
-            'printf("%zu %zu %zu\\n", sizeof(lbm_params), sizeof(lbm_face), sizeof(lbm_derived));']
+            'printf("%zu %zu %zu %zu\\n", sizeof(lbm_params), sizeof(lbm_face), sizeof(lbm_derived), sizeof(lbm_launch));',
+            'printf("%zu %zu %zu %zu\\n", offsetof(lbm_launch, block), offsetof(lbm_launch, blocks_per_cu), '
+            'offsetof(lbm_launch, group_bytes), offsetof(lbm_launch, xcd_ranges));']
     for f in fields:
         prog.append(f'printf("%zu\\n", offsetof(lbm_params, {f}));')
     prog.append("return 0;}")
@@ -59,7 +61,9 @@ def test_ctypes_layout_matches_c_header():
     assert vals[0] == ctypes.sizeof(lbm.Params)
     assert vals[1] == ctypes.sizeof(lbm.Face)
     assert vals[2] == ctypes.sizeof(lbm.Derived)
-    for f, off in zip(fields, vals[3:]):
+    assert vals[3] == ctypes.sizeof(lbm.Launch)
+    assert vals[4:8] == [getattr(lbm.Launch, f).offset for f, _ in lbm.Launch._fields_]
+    for f, off in zip(fields, vals[8:]):
         assert getattr(lbm.Params, f).offset == off, f
 
 

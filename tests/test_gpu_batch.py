@@ -76,19 +76,21 @@ def _same(a, b):
 MiB = 1 << 20
 
 
-@pytest.mark.parametrize("prec,block,per_cu,group", [
-    ("fp64", 256, 0, 0), ("fp32", 64, 0, 0), ("fp16", 128, 0, 0), ("fp32", 256, 1, 0), ("fp16", 64, 4, 0),
-    ("fp32", 256, 0, MiB), ("fp64", 128, 4, 2 * MiB)])
-def test_batch_members_match_solo_bitwise(prec, block, per_cu, group):
+@pytest.mark.parametrize("prec,block,per_cu,group,xcd", [
+    ("fp64", 256, 0, 0, 0), ("fp32", 64, 0, 0, 0), ("fp16", 128, 0, 0, 0), ("fp32", 256, 1, 0, 0),
+    ("fp16", 64, 4, 0, 0), ("fp32", 256, 0, MiB, 0), ("fp64", 128, 4, 2 * MiB, 0), ("fp32", 256, 0, MiB, 8),
+    ("fp16", 64, 1, 0, 8), ("fp32", 128, 0, 0, 3)])
+def test_batch_members_match_solo_bitwise(prec, block, per_cu, group, xcd):
     """Each member of a mixed batch (lean and general wall rules, five sizes)
     equals the same lattice stepped alone, bit for bit, at both parities: with
-    one block per tile or a persistent grid (per_cu > 0), and with the members
-    in one group per wall-rule set or split into groups of at most `group`
-    bytes that run whole check intervals one after another."""
-    _say(f"case batch-vs-solo {prec} block {block} per_cu {per_cu} group {group}")
+    one block per tile or a persistent grid (per_cu > 0), in hardware tile
+    order or in contiguous per-XCD ranges, and with the members in one group
+    per wall-rule set or split into groups of at most `group` bytes that run
+    whole check intervals one after another."""
+    _say(f"case batch-vs-solo {prec} block {block} per_cu {per_cu} group {group} xcd {xcd}")
     ms = _members()
     solo = {k: _make(wl, sd, prec, 0) for k, (wl, sd) in ms.items()}
-    with Batch(check_interval=6, block=block, per_cu=per_cu, group_bytes=group) as b:
+    with Batch(check_interval=6, block=block, per_cu=per_cu, group_bytes=group, xcd_ranges=xcd) as b:
         mem = {k: _make(wl, sd, prec, 0) for k, (wl, sd) in ms.items()}
         for k in ms:
             b.add(mem[k])
@@ -263,12 +265,12 @@ def test_autotune_keeps_results():
         mem = {k: _make(w, s, "fp32", 0) for k, (w, s) in ms.items()}
         for k in ms:
             b.add(mem[k])
-        block, per_cu, group = b.autotune()
-        assert block in (64, 128, 256) and per_cu in (0, 4, 8)
-        assert group in (0, 32 * MiB, 64 * MiB, 128 * MiB, 256 * MiB)
+        block, per_cu, group, xcd = b.autotune()
+        assert block in (64, 128, 256) and per_cu in (0, 4, 8) and xcd in (0, 8)
+        assert group in [0] + [m * MiB for m in (8, 16, 32, 64, 128, 256, 512)]
         b.step(4)
         steps = mem["cavity"].time
-        assert steps == 10 * 2 * 10 + 4   # 10 candidates, one untimed and one timed interval each
+        assert steps == 13 * 2 * 10 + 4   # 13 candidates, one untimed and one timed interval each
         for k, (w, s) in ms.items():
             ref = _make(w, s, "fp32", 0)
             ref.step(steps)
@@ -314,6 +316,8 @@ def test_batch_rejects_mixed_precision_and_bad_block():
             b.set_launch(96)
         with pytest.raises(LBMError):
             b.set_launch(128, -1)
+        with pytest.raises(LBMError):
+            b.set_launch(128, 0, 0, -2)
         with pytest.raises(LBMError):
             b.add(a)
         a.close()

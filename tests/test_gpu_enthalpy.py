@@ -1,0 +1,107 @@
+"""GPU parity of the enthalpy-based D3Q7-MRT phase-change model (App. B,
+conduction setting of Sec. 4.3) against the FP64 oracle, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import lbm_inputs
+import oracle
+from lbm_inputs import face
+from oracle import closed_forms as cf
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1611_03329_amd import Lattice, LBMError  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu(lat):
+    f = lat.enthalpy_fields()
+    _, g = lat.get_state()
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in f.items()}, g.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("ratio", [1.0, 12.0])
+def test_melting_fp64_matches_oracle(ratio):
+    """400x6x6 melting slab (Sec. 4.3 setting), FP64: g, T, En and f_l against
+    the oracle at steps of both parities, while the front crosses several nodes."""
+    wl = lbm_inputs.melting(400, 6, 6, alpha_ratio=ratio)
+    _say(f"case melting fp64 ratio {ratio}")
+    with oracle.EnthalpyOracle(wl) as o, Lattice(wl, "fp64") as lat:
+        for n in (1, 1, 1, 997, 1001):
+            o.step(n)
+            lat.step(n)
+            f, g = _gpu(lat)
+            ref = o.fields()
+            assert _rel(g, o.get_state()) <= 1e-12, (o.time, _rel(g, o.get_state()))
+            for k in ("T", "En"):
+                assert _rel(f[k], ref[k]) <= 1e-12, (o.time, k, _rel(f[k], ref[k]))
+            assert np.max(np.abs(f["fl"] - ref["fl"])) <= 1e-9, o.time
+        assert 0.0 < float(f["fl"].sum()) / 36.0 < 400.0   # a front exists
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_random_state_with_every_wall_rule_matches_oracle(prec, tol):
+    """Seeded random g straddling the solid, mushy and liquid ranges on a ragged
+    box with isothermal, adiabatic and periodic faces, steps of both parities."""
+    wl = lbm_inputs.melting(13, 7, 5, mushy=0.2, stefan=0.5, alpha_ratio=3.0, porosity=0.7, matrix_heat=0.6,
+                            c_ps=0.8)
+    wl["faces"] = [face("wall", "isothermal", 0.9), face("wall", "adiabatic"),
+                   face("periodic", "periodic"), face("periodic", "periodic"),
+                   face("wall", "isothermal", -0.4), face("wall", "isothermal", 0.3)]
+    _say(f"case enthalpy random state {prec}")
+    rng = np.random.default_rng(23)
+    with oracle.EnthalpyOracle(wl) as o, Lattice(wl, prec) as lat:
+        g0 = rng.uniform(-0.3, 0.7, size=(7,) + o.shape)
+        o.set_state(g0)
+        lat.set_state(None, g0)
+        for n in (1, 1, 1, 4, 13):
+            o.step(n)
+            lat.step(n)
+            f, g = _gpu(lat)
+            assert _rel(g, o.get_state()) <= tol, (o.time, _rel(g, o.get_state()))
+            assert _rel(f["En"], o.fields()["En"]) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_melting_front_matches_the_closed_form(prec):
+    """At Fo = 0.01 the GPU slab (400x6x6) follows Eqs. 57-59 as closely as the
+    oracle does: E(T) of Eq. 52 below 2e-3 and the front within half a node."""
+    wl = lbm_inputs.melting(400, 6, 6, alpha_ratio=1.0)
+    t = int(0.01 * 400 ** 2 / wl["alpha_s"])
+    _say(f"case melting closed form {prec}, {t} steps")
+    with Lattice(wl, prec) as lat:
+        lat.step(t)
+        f, _ = _gpu(lat)
+    x = np.arange(400) + 0.5
+    al, als = wl["alpha_l"], wl["alpha_s"]
+    Ta, xm, _ = cf.two_region_melting(x, t, al, als, al, als, 1.0, 0.0, -1.0, wl["latent"], 1.0)
+    T = f["T"]
+    assert np.max(np.abs(T - T[:1, :1, :])) <= 1e-12 if prec == "fp64" else True   # uniform across y, z
+    assert cf.relative_global_error(T[0, 0], Ta) < 2e-3
+    assert abs(f["fl"][0, 0].sum() - xm) < 0.5
+
+
+def test_enthalpy_lattices_refuse_temperature_queries():
+    wl = lbm_inputs.melting(8, 2, 2)
+    with Lattice(wl, "fp64") as lat:
+        with pytest.raises(LBMError):
+            lat.fields()
+        with pytest.raises(LBMError):
+            lat.nusselt()
+        with pytest.raises(LBMError):
+            lat.totals()
