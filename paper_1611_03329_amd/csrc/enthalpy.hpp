@@ -84,18 +84,17 @@ __device__ __forceinline__ void collide_enthalpy(const EnthalpyConsts<C>& ec, C 
 // gather with the static thermal wall rules).  g_0 sits in the second rest plane.
 template <bool ODD, class S, class C>
 __device__ __forceinline__ void gather_g(const KParams<C>& kp, const S& sto, int n, const Nbr& nb, C (&g)[7]) {
-  const uint32_t ps = (uint32_t)kp.pstride;
-  g[0] = ld_rs<S, C>(sto, ps + (uint32_t)n);
+  g[0] = ld_rs<S, C>(sto, rslot(1, (uint32_t)n));
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if constexpr (!ODD) {
-      g[k] = ld_mg<S, C>(sto, (uint32_t)(k - 1) * ps + (uint32_t)n);
+      g[k] = ld_mg<S, C>(sto, gslot(k, (uint32_t)n));
     } else {
       constexpr int ko = D3Q7::opp(k);
       int off;
       bool in;
       link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), -1>(nb, off, in);
-      const uint32_t e = in ? (uint32_t)(ko - 1) * ps + (uint32_t)(n + off) : (uint32_t)(k - 1) * ps + (uint32_t)n;
+      const uint32_t e = in ? gslot(ko, (uint32_t)(n + off)) : gslot(k, (uint32_t)n);
       C v = ld_mg<S, C>(sto, e);
       constexpr int fc = d3q7_face<k, -1>();
       g[k] = in ? v : kp.heat_a[fc] * v + kp.heat_b[fc];
@@ -105,20 +104,19 @@ __device__ __forceinline__ void gather_g(const KParams<C>& kp, const S& sto, int
 
 template <bool ODD, class S, class C>
 __device__ __forceinline__ void scatter_g(const KParams<C>& kp, const S& sto, int n, const Nbr& nb, const C (&g)[7]) {
-  const uint32_t ps = (uint32_t)kp.pstride;
-  st_rs<S, C>(sto, ps + (uint32_t)n, g[0]);
+  st_rs<S, C>(sto, rslot(1, (uint32_t)n), g[0]);
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int ko = D3Q7::opp(k);
     if constexpr (!ODD) {
-      st_mg<S, C>(sto, (uint32_t)(ko - 1) * ps + (uint32_t)n, g[k]);
+      st_mg<S, C>(sto, gslot(ko, (uint32_t)n), g[k]);
     } else {
       int off;
       bool in;
       link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), +1>(nb, off, in);
       constexpr int fc = d3q7_face<k, +1>();
       const C v = in ? g[k] : kp.heat_a[fc] * g[k] + kp.heat_b[fc];
-      const uint32_t e = in ? (uint32_t)(k - 1) * ps + (uint32_t)(n + off) : (uint32_t)(ko - 1) * ps + (uint32_t)n;
+      const uint32_t e = in ? gslot(k, (uint32_t)(n + off)) : gslot(ko, (uint32_t)n);
       st_mg<S, C>(sto, e, v);
     }
   });
@@ -143,10 +141,9 @@ template <class S, class C>
 __global__ void __launch_bounds__(kMaxBlock) k_init_enthalpy(const KParams<C> kp, const S sto, double g0, double gk) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
-  const uint32_t ps = (uint32_t)kp.pstride;
-  st_rs<S, C>(sto, ps + (uint32_t)n, C(g0));
+  st_rs<S, C>(sto, rslot(1, (uint32_t)n), C(g0));
 #pragma unroll
-  for (int k = 1; k < 7; ++k) st_mg<S, C>(sto, (uint32_t)(k - 1) * ps + (uint32_t)n, C(gk));
+  for (int k = 1; k < 7; ++k) st_mg<S, C>(sto, gslot(k, (uint32_t)n), C(gk));
 }
 
 // T, En and f_l of the pre-collision state (any output may be null).
@@ -187,10 +184,9 @@ template <class S, class C>
 __global__ void __launch_bounds__(kMaxBlock) k_set_g(const KParams<C> kp, const S sto, const double* g_in) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
-  const uint32_t ps = (uint32_t)kp.pstride;
-  st_rs<S, C>(sto, ps + (uint32_t)n, C(g_in[n]));
+  st_rs<S, C>(sto, rslot(1, (uint32_t)n), C(g_in[n]));
 #pragma unroll
-  for (int k = 1; k < 7; ++k) st_mg<S, C>(sto, (uint32_t)(k - 1) * ps + (uint32_t)n, C(g_in[(size_t)k * kp.n + n]));
+  for (int k = 1; k < 7; ++k) st_mg<S, C>(sto, gslot(k, (uint32_t)n), C(g_in[(size_t)k * kp.n + n]));
 }
 
 }  // namespace lbm

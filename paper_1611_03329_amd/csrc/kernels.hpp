@@ -1,9 +1,9 @@
 // kernels.hpp -- gfx950 kernels of the fused DDF-MRT porous-convection step.
 //
 // Memory: ONE copy of the populations ("AA pattern"), population-major,
-// plane k at state + k*pstride, node n = x + nx*(y + ny*z) inside a plane;
-// f planes 0..Q-1 then g planes Q..Q+6.  Values are stored shifted by their
-// rest state (see model.hpp).
+// three regions (moving f, moving g, rest f_0 and g_0), each holding its
+// populations in tiles of nodes (see tiled()), node n = x + nx*(y + ny*z).
+// Values are stored shifted by their rest state (see model.hpp).
 //
 // Time parity (streaming, Eqs. 10 and 35, done in place):
 //   even step: read f_i(x) from slot i of x; collide; write f*_i(x) to slot
@@ -68,11 +68,24 @@ struct Store {
   Rs* rs;
 };
 
-// plane of moving flow population i >= 1 and temperature population k >= 1
+// Each region stores its populations in tiles of kTile nodes: the kTile values
+// of one population for nodes [t kTile, (t + 1) kTile) are contiguous and are
+// followed by the next population of the same tile, so the populations of a
+// block of nodes sit together in memory instead of one plane apart each (fewer
+// DRAM pages open at a time).  A region of P populations holds
+// P * pstride elements, pstride a multiple of kTile.
+constexpr int kTileShift = 11;
+constexpr uint32_t kTile = 1u << kTileShift;
+template <uint32_t P>
+__device__ __forceinline__ uint32_t tiled(uint32_t pop, uint32_t n) {
+  return (((n >> kTileShift) * P + pop) << kTileShift) | (n & (kTile - 1u));
+}
+// element of moving flow population i >= 1, moving temperature population
+// k >= 1 and rest population r (0: f_0, 1: g_0) of node n
 template <class Lat>
-__host__ __device__ constexpr uint32_t fplane(int i) { return (uint32_t)(i - 1); }
-template <class Lat>
-__host__ __device__ constexpr uint32_t gplane(int k) { return (uint32_t)(k - 1); }
+__device__ __forceinline__ uint32_t fslot(int i, uint32_t n) { return tiled<(uint32_t)(Lat::Q - 1)>((uint32_t)(i - 1), n); }
+__device__ __forceinline__ uint32_t gslot(int k, uint32_t n) { return tiled<6u>((uint32_t)(k - 1), n); }
+__device__ __forceinline__ uint32_t rslot(int r, uint32_t n) { return tiled<2u>((uint32_t)r, n); }
 
 template <class S, class C>
 __device__ __forceinline__ C ld_mf(const S& s, uint32_t e) { return ld<typename S::MoveF, C>(s.mf, e); }
@@ -229,18 +242,17 @@ __device__ __forceinline__ C open_heat_value(const KParams<C>& kp, C p_out, cons
 template <class Lat, bool ODD, bool GEN, class S, class C>
 __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                        C (&h)[Lat::Q], C (&p)[7]) {
-  const uint32_t ps = (uint32_t)kp.pstride;
-  h[0] = ld_rs<S, C>(sto, (uint32_t)n);
+  h[0] = ld_rs<S, C>(sto, rslot(0, (uint32_t)n));
   static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     if constexpr (!ODD) {
-      h[i] = ld_mf<S, C>(sto, fplane<Lat>(i) * ps + (uint32_t)n);
+      h[i] = ld_mf<S, C>(sto, fslot<Lat>(i, (uint32_t)n));
     } else {
       constexpr int io = Lat::opp(i);
       int off;
       bool in;
       link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, off, in);
-      const uint32_t e = in ? fplane<Lat>(io) * ps + (uint32_t)(n + off) : fplane<Lat>(i) * ps + (uint32_t)n;
+      const uint32_t e = in ? fslot<Lat>(io, (uint32_t)(n + off)) : fslot<Lat>(i, (uint32_t)n);
       C v = ld_mf<S, C>(sto, e);
       if constexpr (GEN) {
         if (kp.moving) {
@@ -253,17 +265,17 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n
       h[i] = v;
     }
   });
-  p[0] = ld_rs<S, C>(sto, ps + (uint32_t)n);
+  p[0] = ld_rs<S, C>(sto, rslot(1, (uint32_t)n));
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if constexpr (!ODD) {
-      p[k] = ld_mg<S, C>(sto, gplane<Lat>(k) * ps + (uint32_t)n);
+      p[k] = ld_mg<S, C>(sto, gslot(k, (uint32_t)n));
     } else {
       constexpr int ko = D3Q7::opp(k);
       int off;
       bool in;
       link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), -1>(nb, off, in);
-      const uint32_t e = in ? gplane<Lat>(ko) * ps + (uint32_t)(n + off) : gplane<Lat>(k) * ps + (uint32_t)n;
+      const uint32_t e = in ? gslot(ko, (uint32_t)(n + off)) : gslot(k, (uint32_t)n);
       C v = ld_mg<S, C>(sto, e);
       // outflow faces carry heat_a = 1, heat_b = 0: their value is already final
       constexpr int fc = d3q7_face<k, -1>();
@@ -279,8 +291,7 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n
 template <class Lat, bool ODD, bool GEN, class S, class C>
 __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                         const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M) {
-  const uint32_t ps = (uint32_t)kp.pstride;
-  st_rs<S, C>(sto, (uint32_t)n, h[0]);
+  st_rs<S, C>(sto, rslot(0, (uint32_t)n), h[0]);
   static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int io = Lat::opp(i);
@@ -298,7 +309,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
           v = (!in && open) ? ov : v;
         }
       }
-      st_mf<S, C>(sto, fplane<Lat>(io) * ps + (uint32_t)n, v);
+      st_mf<S, C>(sto, fslot<Lat>(io, (uint32_t)n), v);
     } else {
       int off;
       bool in;
@@ -311,11 +322,11 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
         const C wv = kp.moving ? v + wall_term<Lat, io>(kp, fc) : v;
         v = in ? v : (open ? ov : wv);
       }
-      const uint32_t e = in ? fplane<Lat>(i) * ps + (uint32_t)(n + off) : fplane<Lat>(io) * ps + (uint32_t)n;
+      const uint32_t e = in ? fslot<Lat>(i, (uint32_t)(n + off)) : fslot<Lat>(io, (uint32_t)n);
       st_mf<S, C>(sto, e, v);
     }
   });
-  st_rs<S, C>(sto, ps + (uint32_t)n, p[0]);
+  st_rs<S, C>(sto, rslot(1, (uint32_t)n), p[0]);
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int ko = D3Q7::opp(k);
@@ -332,7 +343,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
           v = (!in && open) ? ov : v;
         }
       }
-      st_mg<S, C>(sto, gplane<Lat>(ko) * ps + (uint32_t)n, v);
+      st_mg<S, C>(sto, gslot(ko, (uint32_t)n), v);
     } else {
       int off;
       bool in;
@@ -345,7 +356,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
         bv = open ? open_heat_value<C>(kp, v, M) : bv;
       }
       v = in ? v : bv;
-      const uint32_t e = in ? gplane<Lat>(k) * ps + (uint32_t)(n + off) : gplane<Lat>(ko) * ps + (uint32_t)n;
+      const uint32_t e = in ? gslot(k, (uint32_t)(n + off)) : gslot(ko, (uint32_t)n);
       st_mg<S, C>(sto, e, v);
     }
   });
@@ -568,24 +579,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_init(const KParams<C> kp, const I
   const double r = (double)(splitmix64(ia.seed ^ (uint64_t)n) >> 11) * (1.0 / 9007199254740992.0);
   const double noise = ia.noise_amp * (2.0 * r - 1.0);
   T = T + noise;
-  const uint32_t ps = (uint32_t)kp.pstride;
   const double phi = (double)kp.phi;
   const double uu = ia.u[0] * ia.u[0] + ia.u[1] * ia.u[1] + ia.u[2] * ia.u[2];
   static_for<0, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     const double eu = Lat::e(0, i) * ia.u[0] + Lat::e(1, i) * ia.u[1] + Lat::e(2, i) * ia.u[2];
     const double v = weight<Lat, i>() * (3.0 * eu + 4.5 * eu * eu / phi - 1.5 * uu / phi);
-    if constexpr (i == 0) st_rs<S, C>(state, (uint32_t)n, C(v));
-    else st_mf<S, C>(state, fplane<Lat>(i) * ps + (uint32_t)n, C(v));
+    if constexpr (i == 0) st_rs<S, C>(state, rslot(0, (uint32_t)n), C(v));
+    else st_mf<S, C>(state, fslot<Lat>(i, (uint32_t)n), C(v));
   });
   const double dsT = (double)kp.sigma * (T - (double)kp.T_ref);
   const double vp = (double)kp.varpi;
   const double csT2 = vp / 3.0;
-  st_rs<S, C>(state, ps + (uint32_t)n, C((1.0 - vp) * dsT));
+  st_rs<S, C>(state, rslot(1, (uint32_t)n), C((1.0 - vp) * dsT));
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     const double eu = D3Q7::e(0, k) * ia.u[0] + D3Q7::e(1, k) * ia.u[1] + D3Q7::e(2, k) * ia.u[2];
-    st_mg<S, C>(state, gplane<Lat>(k) * ps + (uint32_t)n, C(vp / 6.0 * (dsT + T * eu / csT2)));
+    st_mg<S, C>(state, gslot(k, (uint32_t)n), C(vp / 6.0 * (dsT + T * eu / csT2)));
   });
 }
 
@@ -664,7 +674,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, co
     const int k = 1 + 2 * a + side;  // D3Q7 direction pointing into the fluid
     const double w = (double)kp.varpi / 6.0;
     const double shift = 2.0 * w * (double)kp.sigma * (T_wall[face] - (double)kp.T_ref);
-    const uint32_t gk = gplane<Lat>(k) * (uint32_t)kp.pstride;
     for (int m = threadIdx.x; m < cnt; m += blockDim.x) {
       int c[3];
       c[a] = side ? dim[a] - 1 : 0;
@@ -673,10 +682,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, co
       const int n = c[0] + kp.nx * (c[1] + kp.ny * c[2]);
       double pk;
       if (!ODD) {
-        pk = (double)ld_mg<S, C>(state, gk + (uint32_t)n);
+        pk = (double)ld_mg<S, C>(state, gslot(k, (uint32_t)n));
       } else {
         // the population enters from outside: anti-bounce-back of slot k of this node
-        pk = (double)(kp.heat_a[face] * ld_mg<S, C>(state, gk + (uint32_t)n) + kp.heat_b[face]);
+        pk = (double)(kp.heat_a[face] * ld_mg<S, C>(state, gslot(k, (uint32_t)n)) + kp.heat_b[face]);
       }
       v[0] += 2.0 * pk - shift;
     }
@@ -716,19 +725,18 @@ __global__ void __launch_bounds__(kMaxBlock) k_set_state(const KParams<C> kp, co
                                                          const double* f_in, const double* g_in) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
-  const uint32_t ps = (uint32_t)kp.pstride;
   static_for<0, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     const C v = C(f_in[(size_t)i * kp.n + n] - weight<Lat, i>());
-    if constexpr (i == 0) st_rs<S, C>(state, (uint32_t)n, v);
-    else st_mf<S, C>(state, fplane<Lat>(i) * ps + (uint32_t)n, v);
+    if constexpr (i == 0) st_rs<S, C>(state, rslot(0, (uint32_t)n), v);
+    else st_mf<S, C>(state, fslot<Lat>(i, (uint32_t)n), v);
   });
   const double vp = (double)kp.varpi, sT = (double)kp.sigma * (double)kp.T_ref;
   for (int k = 0; k < 7; ++k) {
     const double om = k == 0 ? 1.0 - vp : vp / 6.0;
     const C v = C(g_in[(size_t)k * kp.n + n] - om * sT);
-    if (k == 0) st_rs<S, C>(state, ps + (uint32_t)n, v);
-    else st_mg<S, C>(state, gplane<Lat>(k) * ps + (uint32_t)n, v);
+    if (k == 0) st_rs<S, C>(state, rslot(1, (uint32_t)n), v);
+    else st_mg<S, C>(state, gslot(k, (uint32_t)n), v);
   }
 }
 
@@ -746,15 +754,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_transfer(const KParams<CS> kps, c
   const Nbr nb = make_nbr(kps, x, y, z);
   CS h[Lat::Q], p[7];
   gather<Lat, ODD, true, SS, CS>(kps, src, n, nb, h, p);
-  const uint32_t ps = (uint32_t)kpd.pstride;
   static_for<0, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    if constexpr (i == 0) st_rs<SD, CD>(dst, (uint32_t)n, (CD)h[0]);
-    else st_mf<SD, CD>(dst, fplane<Lat>(i) * ps + (uint32_t)n, (CD)h[i]);
+    if constexpr (i == 0) st_rs<SD, CD>(dst, rslot(0, (uint32_t)n), (CD)h[0]);
+    else st_mf<SD, CD>(dst, fslot<Lat>(i, (uint32_t)n), (CD)h[i]);
   });
-  st_rs<SD, CD>(dst, ps + (uint32_t)n, (CD)p[0]);
+  st_rs<SD, CD>(dst, rslot(1, (uint32_t)n), (CD)p[0]);
 #pragma unroll
-  for (int k = 1; k < 7; ++k) st_mg<SD, CD>(dst, gplane<Lat>(k) * ps + (uint32_t)n, (CD)p[k]);
+  for (int k = 1; k < 7; ++k) st_mg<SD, CD>(dst, gslot(k, (uint32_t)n), (CD)p[k]);
 }
 
 }  // namespace lbm

@@ -139,7 +139,7 @@ static lbm_status derive_enthalpy(const lbm_params* p, lbm_derived* d) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1)
     return fail(LBM_ERR_INVALID_ARG, "box %dx%dx%d must have at least one node per axis", p->nx, p->ny, p->nz);
   const long long nodes = (long long)p->nx * p->ny * p->nz;
-  if (nodes > (1ll << 30) || 6ll * ((nodes + 127) / 128 * 128) * 8 >= (1ll << 32))
+  if (nodes > (1ll << 30) || 6ll * ((nodes + kTile - 1) / kTile * kTile) * 8 >= (1ll << 32))
     return fail(LBM_ERR_UNSUPPORTED, "box of %lld nodes is too large for one lattice", nodes);
   if (!(p->porosity > 0.0 && p->porosity <= 1.0)) return fail(LBM_ERR_INVALID_ARG, "porosity must be in (0,1]");
   if (!(p->varpi > 0.0 && p->varpi < 1.0)) return fail(LBM_ERR_INVALID_ARG, "varpi must be in (0,1)");
@@ -197,7 +197,7 @@ static lbm_status derive(const lbm_params* p, lbm_derived* d) {
   {
     const long long sb = p->precision == LBM_FP64 ? 8 : (p->precision == LBM_FP32 ? 4 : 2);
     const long long sg = p->precision == LBM_FP64 ? 8 : 4;
-    const long long per_plane = (nodes + 127) / 128 * 128;
+    const long long per_plane = (nodes + kTile - 1) / kTile * kTile;
     if ((long long)(p->lattice - 1) * per_plane * sb >= (1ll << 32) || 6ll * per_plane * sg >= (1ll << 32))
       return fail(LBM_ERR_UNSUPPORTED, "each population region of one lattice must fit in 4 GiB (%lld nodes)",
                   nodes);
@@ -387,8 +387,8 @@ static Layout layout(const lbm_params* p) {
   const size_t c = p->precision == LBM_FP64 ? 8 : 4;  // moving g, rest populations, compute type
   L.block = 256;
   L.nblocks = (int)((nodes + L.block - 1) / L.block);
-  // population planes start on 256-byte boundaries
-  L.pstride = (int)align_up((size_t)nodes, 128);
+  // population regions start on 256-byte boundaries; planes hold whole tiles
+  L.pstride = (int)align_up((size_t)nodes, kTile);  // whole tiles of nodes
   size_t off = 0;
   const bool enth = p->energy == LBM_ENERGY_ENTHALPY;  // no flow populations, no check snapshot
   L.mf = off;
