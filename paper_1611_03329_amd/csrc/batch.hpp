@@ -64,7 +64,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const Member<S, C>* __restri
     stride = (int)gridDim.x;
   }
   for (; t < end; t += stride) {
-    const int m = member_of(mem, nmem, t);
+    // odd steps walk the tiles backwards: they start on the tiles the even
+    // step wrote last, which the last-level cache still holds
+    const int tt = ODD ? ntiles - 1 - t : t;
+    const int m = member_of(mem, nmem, tt);
     // the parameters are read in place: the general wall rules index their
     // per-face arrays with a per-node face number, which a private copy would
     // have to keep in scratch memory
@@ -72,7 +75,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const Member<S, C>* __restri
     const S sto = mem[m].sto;
     C* const snap = mem[m].snap;
     double* const part = mem[m].part;
-    const int lb = t - mem[m].block0;
+    const int lb = tt - mem[m].block0;
     if constexpr (MODE == kModeCompare) {
       // a member that joined after the last snapshot has nothing to compare yet
       if (mem[m].check) step_block<Lat, S, C, ODD, kModeCompare, GEN>(kp, sto, snap, part, lb);
