@@ -315,6 +315,7 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
   k->c_forch = (C)(p->porosity * d->F_phi / std::sqrt(d->K));
   k->l0 = (C)d->l0;
   k->l1 = (C)d->l1;
+  k->l0m = (C)(0.25 * p->porosity * d->nu / d->K);
   k->gbeta = (C)d->gbeta;
   for (int a = 0; a < 3; ++a) k->accel[a] = (C)p->accel[a];
   k->sigma = (C)p->sigma;

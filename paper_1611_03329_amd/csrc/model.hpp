@@ -35,6 +35,7 @@ struct KParams {
   C c_darcy;        // phi nu / K        (Eq. 4)
   C c_forch;        // phi F_phi / sqrt K (Eq. 4)
   C l0, l1;         // Eq. 28
+  C l0m;            // l0 - 1/2 = phi nu / (4 K), the part of l0 that carries the Darcy drag
   C gbeta;          // g beta of Eq. 5
   C accel[3];       // a of Eq. 5
   C sigma, inv_sigma, T_ref, varpi;
@@ -87,11 +88,17 @@ __device__ __forceinline__ Macro<C> macro(const KParams<C>& kp, const C (&h)[Lat
   // Eqs. 27-28 (sum over all directions, rho0 = 1, dt = 1)
   const C hp = C(0.5) * kp.phi;
   const C vx = jx + hp * G[0], vy = jy + hp * G[1], vz = jz + hp * G[2];
+  // u = v / D with D = l0 + sqrt(l0^2 + l1 |v|) = 1 + delta, evaluated as
+  // u = v - v delta / D with delta = 2 (l0 - 1/2) + l1 |v| / D built from its
+  // small parts.  D itself is close to 1: in FP32 its rounding (or that of
+  // l0 ~ 1/2) would shift the drag it carries by up to 1e-4 relative, an
+  // offset the weak Darcy damping then turns into a velocity error of 1e-5.
   const C vn = sqrt(vx * vx + vy * vy + vz * vz);
-  const C inv_den = C(1) / (kp.l0 + sqrt(kp.l0 * kp.l0 + kp.l1 * vn));
-  M.ux = vx * inv_den;
-  M.uy = vy * inv_den;
-  M.uz = vz * inv_den;
+  const C rD = C(1) / (kp.l0 + sqrt(kp.l0 * kp.l0 + kp.l1 * vn));
+  const C q = (C(2) * kp.l0m + kp.l1 * vn * rD) * rD;
+  M.ux = vx - vx * q;
+  M.uy = vy - vy * q;
+  M.uz = vz - vz * q;
   // Eq. 4
   const C un = sqrt(M.ux * M.ux + M.uy * M.uy + M.uz * M.uz);
   const C drag = -(kp.c_darcy + kp.c_forch * un);
