@@ -69,7 +69,9 @@ typedef enum {
   LBM_FP64 = 0,        /* populations stored and computed in FP64 */
   LBM_FP32 = 1,        /* populations stored and computed in FP32 */
   LBM_FP16_STORAGE = 2 /* moving flow populations stored in FP16; temperature and rest
-                          populations in FP32; arithmetic in FP32 */
+                          populations in FP32; arithmetic in FP32.  The FP16 stores round
+                          stochastically (zero-mean error) with random bits hashed from the
+                          lattice's step count, node and population: reproducible runs */
 } lbm_precision;       /* in every mode populations are stored shifted by their rest state */
 
 /* Face rules.  WALL: halfway bounce-back (u_wall: moving wall; a wall velocity

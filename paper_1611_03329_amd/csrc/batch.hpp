@@ -26,6 +26,9 @@ struct Member {
   int block0;     // first tile of the member in the batch's tile list
   int nblocks;    // tiles of the member
   int check;      // the member's snapshot is valid: a compare step compares it
+  // the lattice's step count, one slot per parity: a step at parity p reads
+  // clk[p] and writes clk[p ^ 1] = clk[p] + 1, so no launch reads what it writes
+  uint32_t* clk;
 };
 
 // Member owning block b: members are sorted by block0 and block0 of the first is 0.
@@ -76,19 +79,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const Member<S, C>* __restri
     C* const snap = mem[m].snap;
     double* const part = mem[m].part;
     const int lb = tt - mem[m].block0;
+    uint32_t* const clk = mem[m].clk;
+    const uint32_t now = clk[ODD ? 1 : 0];
+    const uint32_t seed = kStochastic<S> ? mix32(now) : 0u;
+    if (lb == 0 && threadIdx.x == 0) gbl(clk)[ODD ? 0 : 1] = now + 1u;
     if constexpr (MODE == kModeCompare) {
       // a member that joined after the last snapshot has nothing to compare yet
-      if (mem[m].check) step_block<Lat, S, C, ODD, kModeCompare, GEN>(kp, sto, snap, part, lb);
-      else step_block<Lat, S, C, ODD, kModePlain, GEN>(kp, sto, snap, part, lb);
+      if (mem[m].check) step_block<Lat, S, C, ODD, kModeCompare, GEN>(kp, sto, snap, part, lb, seed);
+      else step_block<Lat, S, C, ODD, kModePlain, GEN>(kp, sto, snap, part, lb, seed);
       // the block reduction's shared slots are reused by the next tile
       __syncthreads();
     } else if constexpr (MODE == kModeSpan) {
       // without a snapshot yet the member only takes one
-      if (mem[m].check) step_block<Lat, S, C, ODD, kModeSpan, GEN>(kp, sto, snap, part, lb);
-      else step_block<Lat, S, C, ODD, kModeSnapshot, GEN>(kp, sto, snap, part, lb);
+      if (mem[m].check) step_block<Lat, S, C, ODD, kModeSpan, GEN>(kp, sto, snap, part, lb, seed);
+      else step_block<Lat, S, C, ODD, kModeSnapshot, GEN>(kp, sto, snap, part, lb, seed);
       __syncthreads();
     } else {
-      step_block<Lat, S, C, ODD, MODE, GEN>(kp, sto, snap, part, lb);
+      step_block<Lat, S, C, ODD, MODE, GEN>(kp, sto, snap, part, lb, seed);
     }
   }
 }

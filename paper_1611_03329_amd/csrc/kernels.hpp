@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "model.hpp"
 
@@ -40,15 +41,24 @@ template <class T>
 __device__ __forceinline__ LBM_GLOBAL T* gbl(T* p) {
   return (LBM_GLOBAL T*)p;
 }
+// FP16 populations are stored times 2^12 (exact both ways): departures from
+// the rest state down to 1.5e-8 then lie in FP16's normal range, where it
+// keeps 11 significant bits, and the largest storable departure is 16.
+constexpr float kHalfScale = 4096.0f;
 template <class S, class C>
 __device__ __forceinline__ C ld(const S* base, uint32_t e) {
   const LBM_GLOBAL char* b = (const LBM_GLOBAL char*)base;
-  return static_cast<C>(*(const LBM_GLOBAL S*)(b + e * (uint32_t)sizeof(S)));
+  const S x = *(const LBM_GLOBAL S*)(b + e * (uint32_t)sizeof(S));
+  if constexpr (std::is_same<S, _Float16>::value) return static_cast<C>((float)x * (1.0f / kHalfScale));
+  else return static_cast<C>(x);
 }
 template <class S, class C>
 __device__ __forceinline__ void st(S* base, uint32_t e, C v) {
   LBM_GLOBAL char* b = (LBM_GLOBAL char*)base;
-  *(LBM_GLOBAL S*)(b + e * (uint32_t)sizeof(S)) = static_cast<S>(v);
+  if constexpr (std::is_same<S, _Float16>::value)
+    *(LBM_GLOBAL S*)(b + e * (uint32_t)sizeof(S)) = static_cast<S>((float)v * kHalfScale);
+  else
+    *(LBM_GLOBAL S*)(b + e * (uint32_t)sizeof(S)) = static_cast<S>(v);
 }
 
 // Population storage in three regions: the moving flow populations f_1..f_{Q-1}
@@ -99,6 +109,59 @@ template <class S, class C>
 __device__ __forceinline__ void st_mg(const S& s, uint32_t e, C v) { st<typename S::MoveG, C>(s.mg, e, v); }
 template <class S, class C>
 __device__ __forceinline__ void st_rs(const S& s, uint32_t e, C v) { st<typename S::Rest, C>(s.rs, e, v); }
+
+// FP16 flow storage rounds stochastically: a value goes to one of its two
+// neighbouring FP16 numbers with probability falling linearly with the
+// distance, so the rounding error has zero mean.  Rounding to nearest gives
+// each steady node the same error at every step, a bias that the slow
+// diffusive and Darcy modes accumulate over thousands of steps; a zero-mean
+// error averages out instead.  The random bits are a hash of (step, node)
+// followed by a xorshift sequence over the node's populations, so runs are
+// reproducible bit for bit.
+template <class S>
+constexpr bool kStochastic = std::is_same<typename S::MoveF, _Float16>::value;
+
+// C. Wellons' "lowbias32" integer hash (a bijection of 32-bit words).
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Marsaglia's xorshift32 step (full period over nonzero words).
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+
+// f to FP16 with the random bits r: add a uniform 13-bit integer to the
+// magnitude bits of f below FP16's 10-bit fraction, then cut those 13 bits off,
+// which leaves an FP16 number exactly for magnitudes in FP16's normal range.
+// Below it (2^-14, subnormals: stored departures under 1.5e-8) the conversion
+// then rounds to nearest.  Infinities and the quiet NaN the hardware produces
+// (fraction 0x400000) keep their class: the carry of the added bits never
+// reaches their exponent; magnitudes from 65520 up convert to infinity.
+__device__ __forceinline__ _Float16 half_sr(float f, uint32_t r) {
+  const uint32_t u = __float_as_uint(f);
+  return (_Float16)__uint_as_float((u + (r & 0x1FFFu)) & ~0x1FFFu);
+}
+
+// Store of a moving flow population; with FP16 storage r drives the rounding.
+template <class S, class C>
+__device__ __forceinline__ void st_mf_r(const S& s, uint32_t e, C v, uint32_t r) {
+  if constexpr (kStochastic<S>) {
+    LBM_GLOBAL char* b = (LBM_GLOBAL char*)s.mf;
+    *(LBM_GLOBAL _Float16*)(b + e * 2u) = half_sr((float)v * kHalfScale, r);
+  } else {
+    (void)r;
+    st_mf<S, C>(s, e, v);
+  }
+}
 
 // ------------------------------------------------------------------ geometry
 // Coordinates of node n: exact division by an FP64 reciprocal rounded up
@@ -290,11 +353,23 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n
 // M holds the node's macroscopic state (used by the open-face rules).
 template <class Lat, bool ODD, bool GEN, class S, class C>
 __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
-                                        const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M) {
+                                        const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M, uint32_t seed) {
   st_rs<S, C>(sto, rslot(0, (uint32_t)n), h[0]);
+  // random bits for the stochastic FP16 rounding: one xorshift word serves two
+  // populations (bits 0-12 and 16-28)
+  uint32_t rnd = kStochastic<S> ? (mix32(seed + (uint32_t)n) | 1u) : 0u;
   static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int io = Lat::opp(i);
+    uint32_t r = 0u;
+    if constexpr (kStochastic<S>) {
+      if constexpr (i & 1) {
+        rnd = xorshift32(rnd);
+        r = rnd;
+      } else {
+        r = rnd >> 16;
+      }
+    }
     if constexpr (!ODD) {
       C v = h[i];
       if constexpr (GEN) {
@@ -309,7 +384,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
           v = (!in && open) ? ov : v;
         }
       }
-      st_mf<S, C>(sto, fslot<Lat>(io, (uint32_t)n), v);
+      st_mf_r<S, C>(sto, fslot<Lat>(io, (uint32_t)n), v, r);
     } else {
       int off;
       bool in;
@@ -323,7 +398,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
         v = in ? v : (open ? ov : wv);
       }
       const uint32_t e = in ? fslot<Lat>(i, (uint32_t)(n + off)) : fslot<Lat>(io, (uint32_t)n);
-      st_mf<S, C>(sto, e, v);
+      st_mf_r<S, C>(sto, e, v, r);
     }
   });
   st_rs<S, C>(sto, rslot(1, (uint32_t)n), p[0]);
@@ -413,10 +488,11 @@ constexpr int kPartStride = 8;  // doubles per block in the partials buffer
 //   sum (theta - theta_snap)^2, sum theta^2 and max|u| into part[lb];
 //   MODE 3 does both: it compares with the snapshot, then replaces it.
 // The per-node body of a step: gather, moments, residual bookkeeping,
-// collisions, scatter.  G selects the general wall rules.
+// collisions, scatter.  G selects the general wall rules; seed (a hash of the
+// lattice's step count) drives the stochastic rounding of FP16 storage.
 template <class Lat, class S, class C, bool ODD, int MODE, bool G>
 __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, C* __restrict__ snap, int n,
-                                          const Nbr& nb, double (&red)[5]) {
+                                          const Nbr& nb, double (&red)[5], uint32_t seed) {
   C h[Lat::Q], p[7];
   gather<Lat, ODD, G, S, C>(kp, state, n, nb, h, p);
   const Macro<C> M = macro<Lat, C>(kp, h, p);
@@ -441,7 +517,7 @@ __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, 
   }
   collide_flow<Lat, C>(kp, M, h);
   collide_heat<C>(kp, M, p);
-  scatter<Lat, ODD, G, S, C>(kp, state, n, nb, h, p, M);
+  scatter<Lat, ODD, G, S, C>(kp, state, n, nb, h, p, M, seed);
 }
 
 // Node (x, y, z) lies on a face that moves or is open.
@@ -462,7 +538,7 @@ __device__ __forceinline__ bool on_special_face(const KParams<C>& kp, int x, int
 // the same result for its nodes.  The choice is uniform per wavefront.
 template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
 __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state, C* __restrict__ snap,
-                                           double* __restrict__ part, int lb) {
+                                           double* __restrict__ part, int lb, uint32_t seed) {
   const int n = lb * blockDim.x + threadIdx.x;
   double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (n < kp.n) {
@@ -471,11 +547,11 @@ __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state,
     const Nbr nb = make_nbr(kp, x, y, z);
     if constexpr (GEN) {
       if (__ballot(on_special_face(kp, x, y, z)) != 0)
-        step_node<Lat, S, C, ODD, MODE, true>(kp, state, snap, n, nb, red);
+        step_node<Lat, S, C, ODD, MODE, true>(kp, state, snap, n, nb, red, seed);
       else
-        step_node<Lat, S, C, ODD, MODE, false>(kp, state, snap, n, nb, red);
+        step_node<Lat, S, C, ODD, MODE, false>(kp, state, snap, n, nb, red, seed);
     } else {
-      step_node<Lat, S, C, ODD, MODE, false>(kp, state, snap, n, nb, red);
+      step_node<Lat, S, C, ODD, MODE, false>(kp, state, snap, n, nb, red, seed);
     }
   }
   if constexpr (MODE == kModeCompare || MODE == kModeSpan) {
@@ -718,6 +794,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_get_state(const KParams<C> kp, co
       g_out[(size_t)k * kp.n + n] = (double)p[k] + om * sT;
     }
   }
+}
+
+// Sets slot `slot` of a lattice's step count (the slot the next step reads).
+__global__ void __launch_bounds__(64) k_set_clock(uint32_t* clk, int slot, uint32_t value) {
+  if (threadIdx.x == 0) gbl(clk)[slot] = value;
 }
 
 template <class Lat, class S, class C>

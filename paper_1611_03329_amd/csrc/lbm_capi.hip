@@ -67,6 +67,7 @@ struct lbm_lattice {
   double* part2 = nullptr;  // first-stage fold of part
   int nfold = 0;            // entries in part2
   double* res = nullptr;    // [0..7] residual, [8..13] wall flux, [16..17] totals
+  uint32_t* clk = nullptr;  // [2] step count by parity (drives FP16 stochastic rounding)
   void* dev_member = nullptr; // the lattice as a one-member table for the step kernel
   int* dev_iso = nullptr;   // [6] isothermal flags
   double* dev_Tw = nullptr; // [6] wall temperatures
@@ -377,7 +378,7 @@ static_assert(sizeof(Member<Store<double, double, double>, double>) <= kMemberBy
 static_assert(sizeof(Member<Store<float, float, float>, float>) <= kMemberBytes, "member table entry too large");
 
 struct Layout {
-  size_t mf, mg, rs, snap, part, part2, res, iso, Tw, member, total;
+  size_t mf, mg, rs, snap, part, part2, res, clk, iso, Tw, member, total;
   int pstride, nblocks, block, nfold;
 };
 
@@ -407,6 +408,8 @@ static Layout layout(const lbm_params* p) {
   L.part2 = off;
   off += align_up((size_t)L.nfold * kPartStride * sizeof(double), 256);
   L.res = off;
+  off += 256;
+  L.clk = off;
   off += 256;
   L.iso = off;
   off += 256;
@@ -452,6 +455,15 @@ static S make_store(const lbm_lattice* h) {
   s.mg = static_cast<typename S::MoveG*>(h->mg);
   s.rs = static_cast<typename S::Rest*>(h->rs);
   return s;
+}
+
+static lbm_status launch_check(const char* what);
+
+// The step count read by the next step of a lattice whose state was just
+// written in the even layout (parity 0).
+static lbm_status set_clock(lbm_lattice* h) {
+  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, h->stream, h->clk, 0, (uint32_t)h->t);
+  return launch_check("set_clock");
 }
 
 static lbm_status launch_check(const char* what) {
@@ -514,6 +526,7 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   h->part2 = reinterpret_cast<double*>(base + L.part2);
   h->nfold = L.nfold;
   h->res = reinterpret_cast<double*>(base + L.res);
+  h->clk = reinterpret_cast<uint32_t*>(base + L.clk);
   h->dev_iso = reinterpret_cast<int*>(base + L.iso);
   h->dev_Tw = reinterpret_cast<double*>(base + L.Tw);
   h->dev_member = base + L.member;
@@ -546,12 +559,14 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
     m.snap = static_cast<C*>(h->snap);
     m.part = h->part;
     m.res = h->res;
+    m.clk = h->clk;
     m.block0 = 0;
     m.nblocks = h->nblocks;
     m.check = 1;
     std::memcpy(table, &m, sizeof m);
   });
   if (hipMemsetAsync(h->res, 0, 256, h->stream) != hipSuccess ||
+      hipMemsetAsync(h->clk, 0, 256, h->stream) != hipSuccess ||
       hipMemcpyAsync(h->dev_member, table, sizeof table, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
       hipMemcpyAsync(h->dev_iso, iso, sizeof iso, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
       hipMemcpyAsync(h->dev_Tw, Tw, sizeof Tw, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
@@ -862,7 +877,7 @@ extern "C" lbm_status lbm_set_state(lbm_lattice* h, const double* f, const doubl
   if (ls != LBM_OK) return ls;
   h->parity = 0;
   h->snapshot_valid = false;
-  return LBM_OK;
+  return set_clock(h);
 }
 
 extern "C" lbm_status lbm_enthalpy_fields(lbm_lattice* h, double* T, double* En, double* fl) {
@@ -914,7 +929,7 @@ extern "C" lbm_status lbm_transfer_state(lbm_lattice* dst, lbm_lattice* src) {
   if (ls != LBM_OK) return ls;
   dst->parity = 0;
   dst->snapshot_valid = false;
-  return LBM_OK;
+  return set_clock(dst);
 }
 
 // ------------------------------------------------------------------ batches
@@ -1049,6 +1064,7 @@ static lbm_status batch_upload_typed(lbm_batch* b) {
       m.snap = static_cast<C*>(h->snap);
       m.part = h->part;
       m.res = h->res;
+      m.clk = h->clk;
       m.block0 = cur.tiles;
       m.nblocks = (h->nodes + b->block - 1) / b->block;
       m.check = b->compare_ok[i];

@@ -128,11 +128,11 @@ def _global_rel(a, b):
 
 def test_cavity32_fp32_matches_oracle(cavity32_reference):
     """FP32 storage and arithmetic against the FP64 oracle after 2000 steps,
-    relative global errors of Eq. 52.  T and Nu are within 1e-5; the velocity
-    is not: FP32 rounding of the stored temperature populations (E(T) ~ 4e-6)
-    is amplified about threefold in u through the Darcy-buoyancy balance, so
-    E(u) ~ 1.8e-5 (it stays there at steady state).  The bound below records
-    that measured level; the 1e-5 velocity target is not met in FP32."""
+    relative global errors of Eq. 52: u, T and Nu within 1e-5 (measured
+    2e-7, 1.1e-7, 4e-6).  The velocity bound of 1e-6 also guards the closure
+    of Eq. 28: evaluated as v / (l0 + sqrt(l0^2 + l1|v|)) with l0 ~ 1/2
+    rounded to FP32, the Darcy drag it applies drifts from that of Eq. 4 and
+    E(u) rises to 1.8e-5."""
     wl, ref = cavity32_reference
     _say("case cavity32 fp32")
     with Lattice(wl, "fp32") as lat:
@@ -147,17 +147,20 @@ def test_cavity32_fp32_matches_oracle(cavity32_reference):
     e_T = _global_rel(fl["T"] - wl["T_ref"], r["T"] - wl["T_ref"])
     e_nu = abs(nu[0] - ref[2000]["nu"][0]) / abs(ref[2000]["nu"][0])
     _say("cavity32 fp32: E(u) %.3e E(T) %.3e Nu rel %.3e; max-norm %s" % (e_u, e_T, e_nu, maxn))
-    assert e_T <= 1e-5 and e_nu <= 1e-5
-    assert e_u <= 3e-5
+    assert e_T <= 1e-6 and e_u <= 1e-6
+    assert e_nu <= 1e-5
     assert maxn["rho"] <= 1e-7
 
 
-def test_runs_are_deterministic():
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_runs_are_deterministic(prec):
+    """Two runs give the same state bit for bit (FP16 storage included: its
+    stochastic rounding draws from a hash of step, node and population)."""
     wl = lbm_inputs.cavity(24, seed=5)
-    _say("case determinism 24^3 fp32")
+    _say(f"case determinism 24^3 {prec}")
     outs = []
     for _ in range(2):
-        with Lattice(wl, "fp32", check_interval=10) as lat:
+        with Lattice(wl, prec, check_interval=10) as lat:
             lat.step(101)
             outs.append(_gpu_state(lat))
             outs[-1] += (lat.residual(),)
@@ -245,10 +248,13 @@ def test_random_state_fp32_matches_oracle(q):
 
 
 # ---------------------------------------------------------------- failure path
-def test_unstable_lattice_is_flagged_and_refuses_to_step():
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_unstable_lattice_is_flagged_and_refuses_to_step(prec):
+    """A NaN in the state is found at the next check (in FP16 storage it has to
+    survive the stochastic rounding of every store)."""
     wl = lbm_inputs.cavity(12)
-    _say("case unstable-flag 12^3 fp64 (NaN planted in the state)")
-    with Lattice(wl, "fp64", check_interval=5) as lat:
+    _say(f"case unstable-flag 12^3 {prec} (NaN planted in the state)")
+    with Lattice(wl, prec, check_interval=5) as lat:
         f, g = _gpu_state(lat)
         f[3, 6, 6, 6] = np.nan
         lat.set_state(f, g)
@@ -383,3 +389,22 @@ def test_cavity32_fp16_storage(cavity32_reference):
     _say(f"cavity32 fp16: E(u) {e_u:.3e} E(T) {e_T:.3e} Nu rel {e_nu:.3e}")
     assert e_nu <= 1e-3
     assert e_T <= 1e-3 and e_u <= 1e-2
+
+
+def test_cavity32_fp16_transient_against_fp64():
+    """FP16 storage through the transient of the 32^3 cavity (t = 10000, when
+    Nu still changes): against the FP64 lattice, Nu within 3e-4 and E(T) within
+    2e-5 (measured 2e-5 and 3e-6).  Rounding the FP16 stores to nearest instead
+    of stochastically gives 1.6e-3 and 1.3e-3: each steady node then makes the
+    same rounding error at every step and the slow modes add them up."""
+    wl = lbm_inputs.config_cavity_fp64()
+    _say("case cavity32 fp16 transient t=10000")
+    with Lattice(wl, "fp64") as ref, Lattice(wl, "fp16") as lat:
+        ref.step(10000)
+        lat.step(10000)
+        fr, fl = _gpu_fields(ref), _gpu_fields(lat)
+        nr, nl = ref.nusselt()[0], lat.nusselt()[0]
+    e_T = _global_rel(fl["T"], fr["T"])
+    e_nu = abs(nl - nr) / abs(nr)
+    _say("cavity32 fp16 t=10000: E(T) %.3e Nu rel %.3e" % (e_T, e_nu))
+    assert e_T <= 2e-5 and e_nu <= 3e-4
