@@ -15,6 +15,10 @@ each): 64 cavities of uneven sizes and parameters solved to residual 1e-6 in
 one batch (all arriving at once), or a Poisson stream of cavity solve requests
 served with continuous batching under an HBM budget; both against the same
 solves run one after another in plain FP32.
+
+--workload melting times the enthalpy-based phase-change step (App. B,
+conduction melting of Sec. 4.3) on a 1024x128x128 slab in FP32: 7 populations
+read and written, 56 B per node per step, against the same HBM roofline.
 """
 from __future__ import annotations
 
@@ -159,10 +163,66 @@ def bench_solves(args, kind: str) -> int:
     return 0
 
 
+def bench_melting(args) -> int:
+    """Enthalpy phase-change step (FP32) on a 1024x128x128 melting slab."""
+    import torch
+
+    import lbm_inputs
+    from paper_1611_03329_amd import Lattice
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    wl = lbm_inputs.melting(1024, 128, 128, alpha_ratio=4.0)
+    lat = Lattice(wl, "fp32")
+    nodes = lat.nodes
+    _say(f"{wl['name']}: {nodes} nodes, warmup {args.warmup}")
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    lat.step(args.steps)
+    end.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    ms_per_step = ms / args.steps
+    mlups = nodes * args.steps / (ms / 1e3) / 1e6
+    molten = float(lat.enthalpy_fields()["fl"].sum().item()) / (128 * 128)
+    lat.close()
+    _say(f"{ms_per_step:.4f} ms/step, {mlups:.1f} MLUPS, molten depth {molten:.2f} nodes")
+    achieved = 2 * 7 * 4 * nodes / (ms_per_step / 1e3) / 1e9
+    cpu = None
+    if args.cpu_steps > 0:
+        import oracle
+        small = lbm_inputs.melting(1024, 32, 32, alpha_ratio=4.0)
+        with oracle.EnthalpyOracle(small) as o:
+            t0 = time.perf_counter()
+            o.step(args.cpu_steps)
+            t1 = time.perf_counter()
+        cpu = {"value": 1024 * 32 * 32 * args.cpu_steps / (t1 - t0) / 1e6, "unit": "MLUPS",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"1024x32x32 slab of the same melting problem, FP64 oracle, {args.cpu_steps} steps"}
+    line = {
+        "metric": "MLUPS (D3Q7 enthalpy phase change) & % HBM roofline",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "conduction melting slab 1024x128x128 (Sec. 4.3 setting), enthalpy D3Q7-MRT, "
+                               "FP32, alpha_l/alpha_s 4, St 1", "nodes": nodes, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("cavity256", "batched", "served"), default="cavity256")
+    ap.add_argument("--workload", choices=("cavity256", "batched", "served", "melting"), default="cavity256")
     ap.add_argument("--count", type=int, default=64, help="solves in the batched / served workloads")
     ap.add_argument("--rate", type=float, default=20.0, help="served: mean arrivals per second")
     ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="served: HBM budget for admission")
@@ -182,6 +242,8 @@ def main(argv=None) -> int:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         return 2
+    if args.workload == "melting":
+        return bench_melting(args)
     if args.workload != "cavity256":
         return bench_solves(args, args.workload)
 

@@ -125,7 +125,10 @@ __device__ __forceinline__ void scatter_g(const KParams<C>& kp, const S& sto, in
 template <class S, class C, bool ODD>
 __global__ void __launch_bounds__(kMaxBlock) k_step_enthalpy(const KParams<C> kp, const EnthalpyConsts<C> ec,
                                                              const S sto) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  // odd steps take the blocks in reverse order: they start on the nodes the
+  // even step wrote last, which the last-level cache still holds
+  const int blk = ODD ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+  const int n = blk * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
   int x, y, z;
   node_coords(kp, n, x, y, z);
