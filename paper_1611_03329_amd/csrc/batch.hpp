@@ -52,8 +52,7 @@ __device__ __forceinline__ int member_of(const M* __restrict__ mem, int nmem, in
 // keeps its blocks resident and lets them walk several tiles (a persistent
 // launch).  With nxcd > 1 the grid is a multiple of nxcd.
 template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
-__global__ void __launch_bounds__(kMaxBlock) k_step(const Member<S, C>* __restrict__ mem, int nmem, int ntiles,
-                                                    int nxcd) {
+__device__ __forceinline__ void step_tiles(const Member<S, C>* __restrict__ mem, int nmem, int ntiles, int nxcd) {
   int t, end, stride;
   if (nxcd > 1) {
     const int per = (ntiles + nxcd - 1) / nxcd;
@@ -98,6 +97,29 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const Member<S, C>* __restri
       step_block<Lat, S, C, ODD, MODE, GEN>(kp, sto, snap, part, lb, seed);
     }
   }
+}
+
+// The step kernel with FP32 arithmetic (FP32 and FP16 storage) is held to 128
+// registers, 4 wavefronts per SIMD: the general wall rules alone would need up
+// to 157 and, sharing the kernel with the lean rules, cut every wavefront's
+// occupancy to 3 (the channel ran 12-18 % slower).  With FP64 arithmetic the
+// same limit would spill heavily, so that kernel keeps its own budget.
+template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_step(const Member<S, C>* __restrict__ mem, int nmem, int ntiles, int nxcd) {
+  step_tiles<Lat, S, C, ODD, MODE, GEN>(mem, nmem, ntiles, nxcd);
+}
+template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
+__global__ void __launch_bounds__(kMaxBlock) k_step_fp64(const Member<S, C>* __restrict__ mem, int nmem,
+                                                         int ntiles, int nxcd) {
+  step_tiles<Lat, S, C, ODD, MODE, GEN>(mem, nmem, ntiles, nxcd);
+}
+
+// The step kernel for arithmetic type C.
+template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
+constexpr auto step_kernel() {
+  if constexpr (std::is_same<C, double>::value) return &k_step_fp64<Lat, S, C, ODD, MODE, GEN>;
+  else return &k_step<Lat, S, C, ODD, MODE, GEN>;
 }
 
 // Block m folds member m's partials of the last compare step and forms its

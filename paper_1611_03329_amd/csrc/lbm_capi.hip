@@ -649,11 +649,11 @@ static void launch_step_mode(lbm_lattice* h, const KParams<C>& kp, int mode) {
   const auto* mem = static_cast<const Member<S, C>*>(h->dev_member);
   const dim3 g(h->nblocks), b(h->block);
   if (mode == kModePlain)
-    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModePlain, GEN>), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModePlain, GEN>()), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
   else if (mode == kModeSnapshot)
-    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModeSnapshot, GEN>), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeSnapshot, GEN>()), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
   else
-    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, kModeCompare, GEN>), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeCompare, GEN>()), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
 }
 
 // GEN (moving walls or open faces present) selects the kernels that compile
@@ -1156,10 +1156,10 @@ static void batch_launch_mode(const lbm_batch* b, const lbm_batch::Group& g) {
   const auto* mem = static_cast<const Member<S, C>*>(b->dev_mem) + g.first;
   const int grid = batch_grid(b, g.tiles);
   if (g.gen)
-    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, MODE, true>), dim3(grid), dim3(b->block), 0, b->stream, mem, g.count,
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, true>()), dim3(grid), dim3(b->block), 0, b->stream, mem, g.count,
                        g.tiles, b->nxcd);
   else
-    hipLaunchKernelGGL((k_step<Lat, S, C, ODD, MODE, false>), dim3(grid), dim3(b->block), 0, b->stream, mem, g.count,
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, false>()), dim3(grid), dim3(b->block), 0, b->stream, mem, g.count,
                        g.tiles, b->nxcd);
 }
 
