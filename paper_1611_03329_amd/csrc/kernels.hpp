@@ -260,22 +260,6 @@ __host__ __device__ constexpr double weight() {
   else return Lat::w72(J) / 72.0;
 }
 
-// Moving-wall term of bounce-back for the population entering along direction j:
-// 2 w_j rho0 (e_j . u_w) / cs^2 = 6 w_j (e_j . u_w).
-template <class Lat, int J, class C>
-__device__ __forceinline__ C wall_term(const KParams<C>& kp, int face) {
-  constexpr int ex = Lat::e(0, J), ey = Lat::e(1, J), ez = Lat::e(2, J);
-  C uw[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    C v = kp.u_wall[0][a];
-#pragma unroll
-    for (int f = 1; f < 6; ++f) v = face == f ? kp.u_wall[f][a] : v;
-    uw[a] = v;
-  }
-  return C(6.0 * weight<Lat, J>()) * (C(ex) * uw[0] + C(ey) * uw[1] + C(ez) * uw[2]);
-}
-
 // Open outlet at rho0: the population entering along direction j is the
 // anti-bounce-back of the outgoing post-collision one to twice the even part of
 // f^eq(rho0, u) (Eq. 24 / 18) at the node's own velocity; shifted:
@@ -295,13 +279,102 @@ __device__ __forceinline__ C open_heat_value(const KParams<C>& kp, C p_out, cons
   return -p_out + C(2.0 / 6.0) * kp.varpi * M.dsT;
 }
 
+// ------------------------------------------------------------------ special faces
+// Face f = 2a + s (axis a, s = 0 low, 1 high) is crossed by the link along
+// velocity e taken with sign SG (+1: to x + e, -1: to x - e) when the link's
+// component along a points out of that face.
+template <int EX, int EY, int EZ, int SG>
+constexpr bool crosses(int f) {
+  const int a = f >> 1;
+  const int c = (a == 0 ? EX : (a == 1 ? EY : EZ)) * SG;
+  return (f & 1) ? c > 0 : c < 0;
+}
+
+// Moving-wall term of bounce-back on face f for the population entering along
+// direction j: 2 w_j rho0 (e_j . u_w) / cs^2 = 6 w_j (e_j . u_w), uniform over
+// the face.
+template <class Lat, int J, int F, class C>
+__device__ __forceinline__ C wall_term_face(const KParams<C>& kp) {
+  constexpr int ex = Lat::e(0, J), ey = Lat::e(1, J), ez = Lat::e(2, J);
+  return C(6.0 * weight<Lat, J>()) * (C(ex) * kp.u_wall[F][0] + C(ey) * kp.u_wall[F][1] + C(ez) * kp.u_wall[F][2]);
+}
+
+// Odd-parity gather on moving walls: the population entering node n from
+// outside through a moving face takes the face's wall term.  Face by face,
+// for each special face some node of the wavefront lies on, only the links
+// crossing it; a link crossing several faces takes the rule of its exit face
+// (exit_face: the first wall face crossed, else the first open face), and an
+// open exit face brings a value that is already final.
+template <class Lat, class C>
+__device__ __forceinline__ void gather_walls(const KParams<C>& kp, const Nbr& nb, C (&h)[Lat::Q]) {
+  if (!kp.moving) return;
+  static_for<0, 6>([&](auto F) {
+    constexpr int f = decltype(F)::value;
+    const bool on = !nb.in[f >> 1][f & 1];
+    if (((kp.special >> f) & 1) && __ballot(on) != 0) {
+      static_for<1, Lat::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (crosses<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(f)) {
+          bool open;
+          const int fc = exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, kp.open_flow, open);
+          const C t = wall_term_face<Lat, i, f, C>(kp);
+          h[i] = (on && fc == f && !open) ? h[i] + t : h[i];
+        }
+      });
+    }
+  });
+}
+
+// Scatter on special faces, after the lean scatter has stored every population
+// leaving through a face into this node's own opposite slot (bounce-back): for
+// each special face some node of the wavefront lies on, the populations
+// leaving through it are stored again with their rule applied.  Flow: at odd
+// parity the open-face value or the moving-wall term, at even parity the
+// open-face value (slot ibar of this node is read back only by this node when
+// i leaves through an open face).  Heat: the outflow value, at both parities.
+template <class Lat, bool ODD, class S, class C>
+__device__ __forceinline__ void scatter_faces(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
+                                              const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M,
+                                              uint32_t seed) {
+  static_for<0, 6>([&](auto F) {
+    constexpr int f = decltype(F)::value;
+    const bool on = !nb.in[f >> 1][f & 1];
+    const bool flow = ODD ? ((kp.special >> f) & 1) : ((kp.open_flow >> f) & 1);
+    if (flow && __ballot(on) != 0) {
+      static_for<1, Lat::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (crosses<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(f)) {
+          constexpr int io = Lat::opp(i);
+          bool open;
+          const int fc = exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, kp.open_flow, open);
+          if (on && fc == f && (ODD || open)) {
+            const C v = open ? open_flow_value<Lat, io, C>(h[i], M, kp.inv_phi)
+                             : h[i] + wall_term_face<Lat, io, f, C>(kp);
+            const uint32_t r = mix32(seed + (uint32_t)n * 0x9E3779B9u + (uint32_t)i * 0x85EBCA6Bu);
+            st_mf_r<S, C>(sto, fslot<Lat>(io, (uint32_t)n), v, r);
+          }
+        }
+      });
+    }
+    if (((kp.open_heat >> f) & 1) && __ballot(on) != 0) {
+      static_for<1, 7>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (d3q7_face<k, +1>() == f) {
+          if (on) st_mg<S, C>(sto, gslot(D3Q7::opp(k), (uint32_t)n), open_heat_value<C>(kp, p[k], M));
+        }
+      });
+    }
+  });
+}
+
 // ------------------------------------------------------------------ gather
 // Pre-collision shifted populations of node n at the current parity.  At odd
 // parity a population entering from outside is read from this node's own slot:
 // raw for walls (then the wall rule is applied), already final for open faces
-// (the step that stored it applied the open rule).  GEN = false compiles only
-// the rules of periodic faces and static walls; GEN = true adds moving walls
-// and open faces.
+// (the step that stored it applied the open rule).  The lean rules (periodic
+// faces, static walls, thermal walls) are applied link by link; GEN adds the
+// rules of moving walls and open faces (special faces) as corrections, face by
+// face (gather_walls, scatter_faces).
 template <class Lat, bool ODD, bool GEN, class S, class C>
 __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                        C (&h)[Lat::Q], C (&p)[7]) {
@@ -316,18 +389,10 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n
       bool in;
       link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, off, in);
       const uint32_t e = in ? fslot<Lat>(io, (uint32_t)(n + off)) : fslot<Lat>(i, (uint32_t)n);
-      C v = ld_mf<S, C>(sto, e);
-      if constexpr (GEN) {
-        if (kp.moving) {
-          bool open;
-          const int fc = exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, kp.open_flow, open);
-          const C t = wall_term<Lat, i>(kp, fc);
-          v = (in || open) ? v : v + t;
-        }
-      }
-      h[i] = v;
+      h[i] = ld_mf<S, C>(sto, e);
     }
   });
+  if constexpr (GEN && ODD) gather_walls<Lat, C>(kp, nb, h);
   p[0] = ld_rs<S, C>(sto, rslot(1, (uint32_t)n));
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
@@ -371,34 +436,13 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
       }
     }
     if constexpr (!ODD) {
-      C v = h[i];
-      if constexpr (GEN) {
-        // slot ibar of this node is read back only by this node when i leaves
-        // through an open face: store the open-face value there
-        if (kp.open_flow) {
-          int off;
-          bool in, open;
-          link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, off, in);
-          (void)exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, kp.open_flow, open);
-          const C ov = open_flow_value<Lat, io, C>(v, M, kp.inv_phi);
-          v = (!in && open) ? ov : v;
-        }
-      }
-      st_mf_r<S, C>(sto, fslot<Lat>(io, (uint32_t)n), v, r);
+      st_mf_r<S, C>(sto, fslot<Lat>(io, (uint32_t)n), h[i], r);
     } else {
       int off;
       bool in;
       link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, off, in);
-      C v = h[i];
-      if constexpr (GEN) {
-        bool open;
-        const int fc = exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, kp.open_flow, open);
-        const C ov = open_flow_value<Lat, io, C>(v, M, kp.inv_phi);
-        const C wv = kp.moving ? v + wall_term<Lat, io>(kp, fc) : v;
-        v = in ? v : (open ? ov : wv);
-      }
       const uint32_t e = in ? fslot<Lat>(i, (uint32_t)(n + off)) : fslot<Lat>(io, (uint32_t)n);
-      st_mf_r<S, C>(sto, e, v, r);
+      st_mf_r<S, C>(sto, e, h[i], r);
     }
   });
   st_rs<S, C>(sto, rslot(1, (uint32_t)n), p[0]);
@@ -406,35 +450,18 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
     constexpr int k = decltype(K)::value;
     constexpr int ko = D3Q7::opp(k);
     if constexpr (!ODD) {
-      C v = p[k];
-      if constexpr (GEN) {
-        if (kp.open_heat) {
-          int off;
-          bool in;
-          link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), +1>(nb, off, in);
-          constexpr int fc = d3q7_face<k, +1>();
-          const bool open = (kp.open_heat >> fc) & 1;
-          const C ov = open_heat_value<C>(kp, v, M);
-          v = (!in && open) ? ov : v;
-        }
-      }
-      st_mg<S, C>(sto, gslot(ko, (uint32_t)n), v);
+      st_mg<S, C>(sto, gslot(ko, (uint32_t)n), p[k]);
     } else {
       int off;
       bool in;
       link<D3Q7::e(0, k), D3Q7::e(1, k), D3Q7::e(2, k), +1>(nb, off, in);
-      C v = p[k];
       constexpr int fc = d3q7_face<k, +1>();
-      C bv = kp.heat_a[fc] * v + kp.heat_b[fc];
-      if constexpr (GEN) {
-        const bool open = (kp.open_heat >> fc) & 1;
-        bv = open ? open_heat_value<C>(kp, v, M) : bv;
-      }
-      v = in ? v : bv;
+      const C v = in ? p[k] : kp.heat_a[fc] * p[k] + kp.heat_b[fc];
       const uint32_t e = in ? gslot(k, (uint32_t)(n + off)) : gslot(ko, (uint32_t)n);
       st_mg<S, C>(sto, e, v);
     }
   });
+  if constexpr (GEN) scatter_faces<Lat, ODD, S, C>(kp, sto, n, nb, h, p, M, seed);
 }
 
 // ------------------------------------------------------------------ reductions
