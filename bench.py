@@ -9,12 +9,20 @@ the timed region starts.
 Prints ONE JSON line: MLUPS (whole job), the roofline of the step kernel
 (algorithmic bytes = 2 x 26 populations x 4 B = 208 B per node per step) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
+--precision fp16 runs the same cavity with FP16 flow populations (136 B per
+node per step).
 
 --workload batched | served runs the solve benchmarks instead (one JSON line
 each): 64 cavities of uneven sizes and parameters solved to residual 1e-6 in
 one batch (all arriving at once), or a Poisson stream of cavity solve requests
 served with continuous batching under an HBM budget; both against the same
 solves run one after another in plain FP32.
+
+--workload channel times the 512x128x128 porous channel (D3Q15 flow + D3Q7
+temperature, inflow, open outlet, heated and cooled walls) with FP32 storage
+and with FP16 flow storage side by side, and (unless --cpu-steps 0) their
+errors in u, T and Nu against the FP64 oracle on the 128x32x32 downscale at
+t = 1000 and 2000, the oracle's own run timed as the CPU baseline.
 
 --workload melting times the enthalpy-based phase-change step (App. B,
 conduction melting of Sec. 4.3) on a 1024x128x128 slab in FP32: 7 populations
@@ -163,6 +171,99 @@ def bench_solves(args, kind: str) -> int:
     return 0
 
 
+def _time_steps(lat, warmup: int, steps: int) -> float:
+    """ms per step over `steps` steps after `warmup`, HIP events on the lattice's stream."""
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    lat.step(steps)
+    end.record(lat.stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def bench_channel(args) -> int:
+    """Porous channel 512x128x128, D3Q15 + D3Q7: FP32 and FP16 flow storage."""
+    import numpy as np
+    import torch
+
+    import lbm_inputs
+    from paper_1611_03329_amd import Lattice
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    wl = lbm_inputs.config_channel()
+    runs = {}
+    for prec, bpn in (("fp32", 2 * 22 * 4), ("fp16", 2 * (14 * 2 + 8 * 4))):
+        lat = Lattice(wl, prec, check_interval=args.check_interval)
+        nodes = lat.nodes
+        ms = _time_steps(lat, args.warmup, args.steps)
+        lat.close()
+        gbps = bpn * nodes / (ms / 1e3) / 1e9
+        runs[prec] = {"ms_per_step": round(ms, 5), "mlups": round(nodes / (ms / 1e3) / 1e6, 1),
+                      "bytes_per_node": bpn, "achieved_GBps": round(gbps, 1),
+                      "frac": round(gbps / PEAK_HBM_GBPS, 4)}
+        _say(f"{wl['name']} {prec}: {ms:.4f} ms/step, {runs[prec]['mlups']} MLUPS, {gbps:.0f} GB/s")
+
+    accuracy, cpu = None, None
+    if args.cpu_steps > 0:
+        import oracle
+
+        def fields(lat):
+            f = lat.fields()
+            torch.cuda.synchronize()
+            return {k: v.cpu().numpy() for k, v in f.items()}
+
+        def rel(a, b):
+            return float(np.sqrt(np.sum((a - b) ** 2)) / np.sqrt(np.sum(b ** 2)))
+
+        small = lbm_inputs.config_channel(True)
+        accuracy = {}
+        lats = {p: Lattice(small, p) for p in ("fp32", "fp16")}
+        oracle_s = 0.0
+        with oracle.Oracle(small) as o:
+            for t in (1000, 2000):
+                t0 = time.perf_counter()
+                o.step(t - o.time)
+                oracle_s += time.perf_counter() - t0
+                ref, nu_ref = o.fields(), o.nusselt()[2]
+                u_ref = np.stack([ref["ux"], ref["uy"], ref["uz"]])
+                for p, lat in lats.items():
+                    lat.step(t - lat.time)
+                    f = fields(lat)
+                    nu = lat.nusselt()[2]
+                    accuracy.setdefault(p, {})[f"t{t}"] = {
+                        "E_u": rel(np.stack([f["ux"], f["uy"], f["uz"]]), u_ref),
+                        "E_T": rel(f["T"], ref["T"]), "nu_rel": abs(nu - nu_ref) / abs(nu_ref)}
+            nodes_small = o.n
+        for lat in lats.values():
+            lat.close()
+        _say(f"accuracy against the oracle on {small['name']}: {accuracy}")
+        cpu = {"value": nodes_small * 2000 / oracle_s / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+               "kind": "oracle", "sample": f"{small['name']} downscale, FP64 oracle, 2000 steps"}
+    line = {
+        "metric": "MLUPS (D3Q15+D3Q7 porous channel) & % HBM roofline",
+        "value": runs["fp32"]["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": runs["fp32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "porous channel 512x128x128, D3Q15 MRT flow + D3Q7 MRT temperature, phi 0.7, "
+                               "Da 1e-3, Re 10, Ra 1e5, inflow 0.05, open outlet, seed 3, residual check every "
+                               f"{args.check_interval} steps", "nodes": 512 * 128 * 128, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": runs["fp32"]["achieved_GBps"], "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": runs["fp32"]["frac"], "traffic": None},
+        "fp16_storage": runs["fp16"],
+        "accuracy_vs_oracle": accuracy,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_melting(args) -> int:
     """Enthalpy phase-change step (FP32) on a 1024x128x128 melting slab."""
     import torch
@@ -222,12 +323,15 @@ def bench_melting(args) -> int:
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("cavity256", "batched", "served", "melting"), default="cavity256")
+    ap.add_argument("--workload", choices=("cavity256", "batched", "served", "channel", "melting"),
+                    default="cavity256")
     ap.add_argument("--count", type=int, default=64, help="solves in the batched / served workloads")
     ap.add_argument("--rate", type=float, default=20.0, help="served: mean arrivals per second")
     ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="served: HBM budget for admission")
     ap.add_argument("--max-steps", type=int, default=100_000, help="solves: step cap per solve")
     ap.add_argument("--tune-count", type=int, default=16, help="solves: workloads used to tune the launch shape")
+    ap.add_argument("--precision", choices=("fp32", "fp16"), default="fp32",
+                    help="cavity256: population storage (FP16 flow populations, FP32 arithmetic)")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--check-interval", type=int, default=100)
@@ -244,6 +348,8 @@ def main(argv=None) -> int:
         return 2
     if args.workload == "melting":
         return bench_melting(args)
+    if args.workload == "channel":
+        return bench_channel(args)
     if args.workload != "cavity256":
         return bench_solves(args, args.workload)
 
@@ -275,7 +381,7 @@ def main(argv=None) -> int:
         del a, b
         torch.cuda.empty_cache()
     wl = lbm_inputs.config_cavity_fp32()
-    lat = Lattice(wl, "fp32", check_interval=args.check_interval)
+    lat = Lattice(wl, args.precision, check_interval=args.check_interval)
     nodes = lat.nodes
     print(f"[bench] {wl['name']}: {nodes} nodes, warmup {args.warmup}", file=sys.stderr, flush=True)
     lat.step(args.warmup)
@@ -296,9 +402,10 @@ def main(argv=None) -> int:
     print(f"[bench] {ms_per_step:.4f} ms/step, {mlups:.1f} MLUPS, residual {r:.3e} at {at}, "
           f"Nu_hot {nu[0]:.5f}", file=sys.stderr, flush=True)
 
-    bytes_per_node = 2 * (19 + 7) * 4
+    fp16 = args.precision == "fp16"
+    bytes_per_node = 2 * (18 * 2 + 8 * 4) if fp16 else 2 * (19 + 7) * 4
     achieved = bytes_per_node * nodes / (ms_per_step / 1e3) / 1e9
-    traffic = traffic_from_profiles(nodes)
+    traffic = None if fp16 else traffic_from_profiles(nodes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
                 "copy_reference_GBps": None if copy_gbps is None else round(copy_gbps, 1)}
@@ -322,8 +429,9 @@ def main(argv=None) -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "porous cavity 256^3, D3Q19 MRT flow + D3Q7 MRT temperature, FP32, "
-                        "phi 0.4, Da 1e-4, Ra 1e6, Pr 1, seed 2, residual check every "
+            "workload": "porous cavity 256^3, D3Q19 MRT flow + D3Q7 MRT temperature, "
+                        + ("FP16 flow storage (stochastic rounding), FP32 arithmetic, " if fp16 else "FP32, ")
+                        + "phi 0.4, Da 1e-4, Ra 1e6, Pr 1, seed 2, residual check every "
                         f"{args.check_interval} steps",
             "nodes": nodes,
             "parallelism": "single GPU",
