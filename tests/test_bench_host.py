@@ -1,0 +1,25 @@
+"""Host-side behaviour of bench.py that needs no GPU."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_the_traffic_profile_names_the_kernel_it_was_taken_on():
+    """The counter summary the bench line reads carries the hash of the
+    kernel sources it was measured on, and a byte count per launch of the
+    right size (the 208 B/node algorithmic bytes, within a few per cent)."""
+    with open(os.path.join(ROOT, "profiles", "step_cavity256_fp32_traffic.json")) as f:
+        rec = json.load(f)
+    assert len(rec["kernel_hash"]) == 16 and int(rec["kernel_hash"], 16) >= 0
+    algorithmic = 208 * rec["nodes"]
+    assert 1.0 <= rec["bytes_per_launch"] / algorithmic < 1.05
