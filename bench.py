@@ -343,7 +343,7 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); there is no "
               "multi-GPU path", file=sys.stderr)
         return 2
     if args.workload == "melting":

@@ -62,7 +62,7 @@ typedef enum {
   LBM_ERR_OUT_OF_MEMORY = 2, /* device allocation failed or caller buffer too small */
   LBM_ERR_DEVICE = 3,        /* a HIP call failed */
   LBM_ERR_UNSTABLE = 4,      /* a check found a non-finite value or |u| > 0.5 (sticky) */
-  LBM_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
+  LBM_ERR_UNSUPPORTED = 5    /* valid request that is not implemented */
 } lbm_status;
 
 typedef enum {
