@@ -168,6 +168,25 @@ def test_runs_are_deterministic(prec):
     assert outs[0][2] == outs[1][2]
 
 
+def test_set_state_continues_the_fp16_trajectory():
+    """A lattice handed another's state at the same time continues its FP16
+    trajectory bit for bit, although it restarts from the other parity of the
+    AA layout: the stochastic rounding draws from the lattice's step count,
+    which set_state keeps."""
+    wl = lbm_inputs.cavity(24, seed=6)
+    _say("case fp16 set_state continuation 24^3")
+    with Lattice(wl, "fp16") as a, Lattice(wl, "fp16") as b:
+        a.step(37)
+        b.step(37)
+        f, g = a.get_state()
+        b.set_state(f, g)
+        a.step(25)
+        b.step(25)
+        fa, ga = _gpu_state(a)
+        fb, gb = _gpu_state(b)
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
 # ---------------------------------------------------------------- random states, ragged boxes
 def _box(shape, q, faces, **kw):
     wl = lbm_inputs.cavity(shape, lattice=q, porosity=0.55, darcy=5e-3, rayleigh=2e5, **kw)
