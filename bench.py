@@ -16,7 +16,9 @@ node per step).
 each): 64 cavities of uneven sizes and parameters solved to residual 1e-6 in
 one batch (all arriving at once), or a Poisson stream of cavity solve requests
 served with continuous batching under an HBM budget; both against the same
-solves run one after another in plain FP32.
+solves run one after another in plain FP32.  The server runs first come first
+served (FP32, then FP16 storage with an FP32 finish) and smallest first under
+a resident-node cap (FP32).
 
 --workload channel times the 512x128x128 porous channel (D3Q15 flow + D3Q7
 temperature, inflow, open outlet, heated and cooled walls) with FP32 storage
@@ -132,14 +134,16 @@ def bench_solves(args, kind: str) -> int:
     shape = tune_launch([q.workload for q in reqs[:args.tune_count]], "fp32", 100)
     _say(f"launch shape (threads, blocks/CU, group bytes) = {shape}")
     runs = {}
-    for prec in ("fp32", "fp16"):
+    cap = int(args.smallest_first_mnodes * 1e6)
+    for name, prec, policy, max_nodes in (("fp32", "fp32", "fcfs", None), ("fp16", "fp16", "fcfs", None),
+                                          ("fp32_smallest_first", "fp32", "smallest", cap)):
         with Server(prec, check_interval=100, tol=1e-6, max_steps=args.max_steps, hbm_budget=budget,
-                    launch=shape) as srv:
+                    launch=shape, policy=policy, max_nodes=max_nodes) as srv:
             res = srv.run(reqs, progress=_say)
             stats = dict(srv.stats)
-        runs[prec] = (res, {**summarize(res), "promoted": stats["promoted"],
+        runs[name] = (res, {**summarize(res), "promoted": stats["promoted"],
                             "peak_members": stats["peak_members"], "peak_bytes": stats["peak_bytes"]})
-        _say(f"served {prec}: {runs[prec][1]}")
+        _say(f"served {name}: {runs[name][1]}")
     seq = solve_sequential(reqs, "fp32", check_interval=100, tol=1e-6, max_steps=args.max_steps, progress=_say)
     q_sum = summarize(seq)
     _say(f"sequential fp32: {q_sum}")
@@ -163,6 +167,7 @@ def bench_solves(args, kind: str) -> int:
                    "max_steps": args.max_steps, "launch": list(shape), "parallelism": "single GPU"},
         "served_fp32": main_sum,
         "served_fp16_then_fp32": runs["fp16"][1],
+        "served_fp32_smallest_first": {**runs["fp32_smallest_first"][1], "max_resident_nodes": cap},
         "sequential_fp32": q_sum,
         "speedup_solves_per_s": {p: round(runs[p][1]["solves_per_s"] / q_sum["solves_per_s"], 3) for p in runs},
         "nu_hot_rel_diff_vs_sequential": {p: nu_diff(runs[p][0]) for p in runs},
@@ -330,6 +335,8 @@ def main(argv=None) -> int:
     ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="served: HBM budget for admission")
     ap.add_argument("--max-steps", type=int, default=100_000, help="solves: step cap per solve")
     ap.add_argument("--tune-count", type=int, default=16, help="solves: workloads used to tune the launch shape")
+    ap.add_argument("--smallest-first-mnodes", type=float, default=24.0,
+                    help="solves: resident-node cap (millions) of the smallest-first serving run")
     ap.add_argument("--precision", choices=("fp32", "fp16"), default="fp32",
                     help="cavity256: population storage (FP16 flow populations, FP32 arithmetic)")
     ap.add_argument("--steps", type=int, default=2000)

@@ -5,8 +5,11 @@ A request is one porous-cavity (or channel) workload to be run until its
 residual r (the relative change of u and of theta over one step, checked every
 K steps on the GPU) falls below a tolerance.  The server
 
-  * admits arrived requests first come, first served, while their device bytes
-    (lbm_required_bytes) fit the HBM budget and a member slot is free;
+  * admits arrived requests while their device bytes (lbm_required_bytes) fit
+    the HBM budget, a member slot is free and (optionally) the resident nodes
+    stay under a cap: first come, first served, or smallest first (the
+    request with the fewest nodes that fits, a shortest-job-first proxy that
+    lets short solves pass long ones when the GPU is oversubscribed);
   * keeps every admitted state resident in device memory and steps all of
     them together, one batch launch per time step, K steps per host
     round-trip (replayed from a HIP graph when enabled);
@@ -106,11 +109,18 @@ class Server:
 
     def __init__(self, precision: str = "fp32", check_interval: int = 100, tol: float = 1e-6,
                  max_steps: int = 200_000, hbm_budget: int | None = None, max_members: int = 256,
-                 graph: bool = True, launch: tuple | None = None, plateau: tuple = (0.9, 5), device=None):
+                 graph: bool = True, launch: tuple | None = None, plateau: tuple = (0.9, 5), device=None,
+                 policy: str = "fcfs", max_nodes: int | None = None):
         if check_interval <= 0 or check_interval % 2:
             raise ValueError("check_interval must be a positive even number (chunks keep the parity)")
         if precision not in ("fp32", "fp16"):
             raise ValueError("precision must be fp32 or fp16")
+        if policy not in ("fcfs", "smallest"):
+            raise ValueError("policy must be fcfs or smallest")
+        self.policy = policy
+        # cap on the nodes resident at once (None: only the HBM budget limits);
+        # a request larger than the cap still runs, alone
+        self.max_nodes = None if max_nodes is None else int(max_nodes)
         self.precision = precision
         self.K = int(check_interval)
         self.chunk = self.K
@@ -155,6 +165,7 @@ class Server:
             # an FP16 solve reserves room for its FP32 copy as well, so that its
             # move can never wait for memory
             need[q.rid]["admit"] = sum(need[q.rid].values()) if first == "fp16" else need[q.rid]["fp32"]
+            need[q.rid]["nodes"] = q.workload["nx"] * q.workload["ny"] * q.workload["nz"]
             if need[q.rid]["admit"] > self.hbm_budget:
                 raise ValueError(f"request {q.rid} needs more than the HBM budget")
         waiting = deque()
@@ -162,6 +173,11 @@ class Server:
         results = {}
         used = 0
         t0 = clock()
+
+        def next_admission():
+            return pick_admission(list(waiting), need, self.policy, len(active),
+                                  sum(e["lat"].nodes for e in active.values()), used,
+                                  self.hbm_budget, self.max_members, self.max_nodes)
 
         def retire(lat, e):
             nonlocal used
@@ -181,10 +197,12 @@ class Server:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            # admission, first come first served, between chunks
-            while (waiting and len(active) < self.max_members
-                   and used + need[waiting[0].rid]["admit"] <= self.hbm_budget):
-                q = waiting.popleft()
+            # admission, between chunks
+            while True:
+                q = next_admission()
+                if q is None:
+                    break
+                waiting.remove(q)
                 lat = Lattice(q.workload, first, device=self.device)
                 self.batches[first].add(lat)
                 res = Result(q.rid, q.workload.get("name", ""), lat.nodes, q.arrival, admitted=clock() - t0)
@@ -240,6 +258,29 @@ class Server:
                 active[id(new)] = e
                 self.stats["promoted"] += 1
         return [results[q.rid] for q in requests]
+
+
+def pick_admission(waiting: list, need: dict, policy: str, n_active: int, resident_nodes: int, used: int,
+                   budget: int, max_members: int, max_nodes: int | None):
+    """The waiting request (arrival order) to admit next, or None.  need[rid]
+    holds its bytes to reserve ("admit") and its nodes.  A request fits while
+    a member slot is free, its bytes fit the budget and, with a node cap, the
+    resident nodes stay under the cap (a request alone always fits the cap).
+    "fcfs" admits the head of the queue only; "smallest" the fitting request
+    with the fewest nodes (ties: earliest arrival)."""
+    def fits(q) -> bool:
+        if n_active >= max_members or used + need[q.rid]["admit"] > budget:
+            return False
+        return max_nodes is None or n_active == 0 or resident_nodes + need[q.rid]["nodes"] <= max_nodes
+
+    if not waiting:
+        return None
+    if policy == "fcfs":
+        return waiting[0] if fits(waiting[0]) else None
+    for q in sorted(waiting, key=lambda q: (need[q.rid]["nodes"], q.arrival)):
+        if fits(q):
+            return q
+    return None
 
 
 def solve_sequential(requests: list, precision: str = "fp32", check_interval: int = 100, tol: float = 1e-6,

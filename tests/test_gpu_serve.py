@@ -103,3 +103,24 @@ def test_fp16_promotion_respects_the_budget():
         assert srv.stats["peak_bytes"] <= budget
         assert srv.stats["promoted"] == len(reqs)
     assert all(r.converged for r in res)
+
+
+def test_smallest_first_under_a_node_cap():
+    """Smallest first with a resident-node cap of two small requests: the
+    requests are admitted in order of size, the cap holds, and every result
+    is still the one the request gets alone (fp32, bit for bit)."""
+    reqs = _requests()
+    sizes = sorted(q.workload["nx"] * q.workload["ny"] * q.workload["nz"] for q in reqs)
+    cap = sizes[0] + sizes[1]
+    _say(f"case smallest first, node cap {cap}")
+    with Server("fp32", policy="smallest", max_nodes=cap, **KW) as srv:
+        res = srv.run(reqs)
+    assert all(r.converged for r in res)
+    # every request after the first was admitted when it fitted the cap; the
+    # order of admission is the order of size among those waiting
+    order = [r.nodes for r in sorted(res, key=lambda r: r.admitted)]
+    assert order[1:] == sorted(order[1:]) or order == sorted(order), order
+    with Server("fp32", **KW) as srv2:
+        ref = srv2.run(reqs)
+    for a, b in zip(res, ref):
+        assert (a.steps, a.checked_at, a.residual, a.nu) == (b.steps, b.checked_at, b.residual, b.nu), a.rid

@@ -30,3 +30,28 @@ def test_requests_sorted_by_arrival_and_summary():
     assert abs(s["makespan_s"] - (0.99 + 1.99)) < 1e-9
     assert abs(s["mlups"] - 100 * 1000 * 200 / (0.99 + 1.99) / 1e6) < 1e-9
     assert isinstance(Request(0, 0.0, {}), Request)
+
+
+def test_admission_policies():
+    """First come first served admits only the head of the queue; smallest
+    first takes the fitting request with the fewest nodes; a node cap holds
+    requests back unless nothing is resident."""
+    from paper_1611_03329_amd.serve import pick_admission
+    qs = [Request(0, 0.0, {}), Request(1, 0.1, {}), Request(2, 0.2, {})]
+    need = {0: {"admit": 800, "nodes": 8000}, 1: {"admit": 100, "nodes": 1000}, 2: {"admit": 300, "nodes": 3000}}
+    # budget 1000, 500 bytes in use: the head (800) does not fit
+    assert pick_admission(qs, need, "fcfs", 1, 5000, 500, 1000, 10, None) is None
+    assert pick_admission(qs, need, "smallest", 1, 5000, 500, 1000, 10, None).rid == 1
+    # nothing in use: fcfs takes the head, smallest the smallest
+    assert pick_admission(qs, need, "fcfs", 0, 0, 0, 1000, 10, None).rid == 0
+    assert pick_admission(qs, need, "smallest", 0, 0, 0, 1000, 10, None).rid == 1
+    # node cap 4500 with 2000 resident: 1 (1000) fits, 2 (3000) does not
+    assert pick_admission(qs[2:], need, "smallest", 1, 2000, 0, 10_000, 10, 4500) is None
+    assert pick_admission(qs[1:], need, "smallest", 1, 2000, 0, 10_000, 10, 4500).rid == 1
+    # an empty GPU takes a request larger than the cap
+    assert pick_admission(qs[:1], need, "smallest", 0, 0, 0, 10_000, 10, 4500).rid == 0
+    # no free member slot
+    assert pick_admission(qs, need, "smallest", 3, 0, 0, 10_000, 3, None) is None
+    # ties by arrival
+    need2 = {0: {"admit": 1, "nodes": 5}, 1: {"admit": 1, "nodes": 5}}
+    assert pick_admission(qs[:2], need2, "smallest", 0, 0, 0, 10, 10, None).rid == 0
