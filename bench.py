@@ -10,7 +10,10 @@ Prints ONE JSON line: MLUPS (whole job), the roofline of the step kernel
 (algorithmic bytes = 2 x 26 populations x 4 B = 208 B per node per step) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
 --precision fp16 runs the same cavity with FP16 flow populations (136 B per
-node per step).
+node per step).  That step is limited by vector instruction issue rather than
+by HBM: the line adds its VALU issue rate (wave64 VALU instructions per CU per
+clock at 2.4 GHz, the instruction count per step taken from the committed
+counter profile).
 
 --workload batched | served runs the solve benchmarks instead (one JSON line
 each): 64 cavities of uneven sizes and parameters solved to residual 1e-6 in
@@ -44,6 +47,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (D3Q19+D3Q7) & % HBM roofline; batched-solve p50/p99 latency"
 PEAK_HBM_GBPS = 8000.0
+# nominal vector instruction issue: one wave64 VALU instruction per CU per
+# clock (four SIMDs, four clocks each), 256 CUs at 2.4 GHz
+PEAK_VALU_WAVE_INSTR_PER_S = 256 * 2.4e9
 # everything the step kernel is compiled from, build flags included
 KERNEL_SOURCES = ("paper_1611_03329_amd/csrc/kernels.hpp", "paper_1611_03329_amd/csrc/model.hpp",
                   "paper_1611_03329_amd/csrc/lattice.hpp", "paper_1611_03329_amd/csrc/batch.hpp",
@@ -69,6 +75,20 @@ def traffic_from_profiles(nodes: int):
     if rec.get("kernel_hash") != kernel_hash() or rec.get("nodes") != nodes:
         return None
     return rec.get("bytes_per_launch")
+
+
+def valu_from_profiles(nodes: int, precision: str):
+    """Wave-level VALU instructions per step of the whole lattice (mean of the
+    two parities' step kernels) from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"step_cavity256_{precision}_valu.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash() or rec.get("nodes") != nodes:
+        return None
+    return rec.get("valu_per_step")
 
 
 def cpu_baseline(workload: dict, steps: int) -> dict:
@@ -416,6 +436,13 @@ def main(argv=None) -> int:
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
                 "copy_reference_GBps": None if copy_gbps is None else round(copy_gbps, 1)}
+    if fp16:
+        # FP16 mode issues more vector instructions per node than the HBM time
+        # of its 136 bytes covers: report the issue rate beside the bytes
+        valu = valu_from_profiles(nodes, "fp16")
+        roofline["valu_issue"] = None if valu is None else {
+            "wave_instructions_per_step": valu,
+            "per_cu_per_clock": round(valu / (ms_per_step / 1e3) / PEAK_VALU_WAVE_INSTR_PER_S, 4)}
 
     cpu = None
     if args.cpu_steps > 0:

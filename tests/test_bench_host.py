@@ -23,3 +23,17 @@ def test_the_traffic_profile_names_the_kernel_it_was_taken_on():
     assert len(rec["kernel_hash"]) == 16 and int(rec["kernel_hash"], 16) >= 0
     algorithmic = 208 * rec["nodes"]
     assert 1.0 <= rec["bytes_per_launch"] / algorithmic < 1.05
+
+
+def test_the_valu_profile_names_the_kernel_it_was_taken_on():
+    """The FP16-mode instruction counts the bench line reads carry the same
+    kernel hash as the traffic profile and lie between the static counts of
+    the two parities' kernels' lean paths (about 600 to 1200 per wavefront)."""
+    with open(os.path.join(ROOT, "profiles", "step_cavity256_fp16_valu.json")) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, "profiles", "step_cavity256_fp32_traffic.json")) as f:
+        traffic = json.load(f)
+    assert rec["kernel_hash"] == traffic["kernel_hash"]
+    waves = rec["nodes"] // 64
+    assert 600 <= rec["even_valu"] / waves < rec["odd_valu"] / waves <= 1200
+    assert rec["valu_per_step"] == (rec["even_valu"] + rec["odd_valu"]) / 2
