@@ -355,7 +355,7 @@ def main(argv=None) -> int:
     ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="served: HBM budget for admission")
     ap.add_argument("--max-steps", type=int, default=100_000, help="solves: step cap per solve")
     ap.add_argument("--tune-count", type=int, default=16, help="solves: workloads used to tune the launch shape")
-    ap.add_argument("--smallest-first-mnodes", type=float, default=24.0,
+    ap.add_argument("--smallest-first-mnodes", type=float, default=4.0,
                     help="solves: resident-node cap (millions) of the smallest-first serving run")
     ap.add_argument("--precision", choices=("fp32", "fp16"), default="fp32",
                     help="cavity256: population storage (FP16 flow populations, FP32 arithmetic)")
