@@ -70,7 +70,6 @@ struct lbm_lattice {
   uint32_t* clk = nullptr;  // [2] step count by parity (drives FP16 stochastic rounding)
   void* dev_member = nullptr; // the lattice as a one-member table for the step kernel
   int* dev_iso = nullptr;   // [6] isothermal flags
-  double* dev_Tw = nullptr; // [6] wall temperatures
   double* host_res = nullptr; // pinned mirror of res (32 doubles)
   int parity = 0;
   int64_t t = 0;
@@ -378,7 +377,7 @@ static_assert(sizeof(Member<Store<double, double, double>, double>) <= kMemberBy
 static_assert(sizeof(Member<Store<float, float, float>, float>) <= kMemberBytes, "member table entry too large");
 
 struct Layout {
-  size_t mf, mg, rs, snap, part, part2, res, clk, iso, Tw, member, total;
+  size_t mf, mg, rs, snap, part, part2, res, clk, iso, member, total;
   int pstride, nblocks, block, nfold;
 };
 
@@ -412,8 +411,6 @@ static Layout layout(const lbm_params* p) {
   L.clk = off;
   off += 256;
   L.iso = off;
-  off += 256;
-  L.Tw = off;
   off += 256;
   L.member = off;
   off += kMemberBytes;
@@ -528,16 +525,13 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   h->res = reinterpret_cast<double*>(base + L.res);
   h->clk = reinterpret_cast<uint32_t*>(base + L.clk);
   h->dev_iso = reinterpret_cast<int*>(base + L.iso);
-  h->dev_Tw = reinterpret_cast<double*>(base + L.Tw);
   h->dev_member = base + L.member;
   fill_kparams<double>(p, &d, h->nodes, h->pstride, &h->kd);
   fill_kparams<float>(p, &d, h->nodes, h->pstride, &h->kf);
 
   int iso[6];
-  double Tw[6];
   for (int f = 0; f < 6; ++f) {
     iso[f] = p->face[f].heat == LBM_HEAT_ISOTHERMAL;
-    Tw[f] = p->face[f].T_wall;
   }
   lbm_status st_ = LBM_OK;
   auto cleanup = [&]() {
@@ -568,8 +562,7 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   if (hipMemsetAsync(h->res, 0, 256, h->stream) != hipSuccess ||
       hipMemsetAsync(h->clk, 0, 256, h->stream) != hipSuccess ||
       hipMemcpyAsync(h->dev_member, table, sizeof table, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-      hipMemcpyAsync(h->dev_iso, iso, sizeof iso, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-      hipMemcpyAsync(h->dev_Tw, Tw, sizeof Tw, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+      hipMemcpyAsync(h->dev_iso, iso, sizeof iso, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
     cleanup();
     return fail(LBM_ERR_DEVICE, "initial copies failed");
   }
@@ -755,9 +748,9 @@ extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {
     using C = decltype(c_t);
     const S st_ = make_store<S>(h);
     if (h->parity)
-      hipLaunchKernelGGL((k_wall_flux<Lat, S, C, true>), dim3(6), dim3(256), 0, h->stream, kp, st_, h->dev_iso, h->dev_Tw, h->res + 8);
+      hipLaunchKernelGGL((k_wall_flux<Lat, S, C, true>), dim3(6), dim3(256), 0, h->stream, kp, st_, h->dev_iso, h->res + 8);
     else
-      hipLaunchKernelGGL((k_wall_flux<Lat, S, C, false>), dim3(6), dim3(256), 0, h->stream, kp, st_, h->dev_iso, h->dev_Tw, h->res + 8);
+      hipLaunchKernelGGL((k_wall_flux<Lat, S, C, false>), dim3(6), dim3(256), 0, h->stream, kp, st_, h->dev_iso, h->res + 8);
   });
   lbm_status ls = launch_check("wall flux");
   if (ls != LBM_OK) return ls;

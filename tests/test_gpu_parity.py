@@ -301,6 +301,41 @@ def test_cavity256_fp32_two_steps_match_oracle():
         assert err <= 1e-5, (k, err)
 
 
+@pytest.fixture(scope="module")
+def cavity256_fp64_gpu():
+    """The measured workload after 400 steps with FP64 storage and arithmetic
+    on the GPU (the path that matches the oracle to 1e-13 on the cavities the
+    oracle can run this long)."""
+    wl = lbm_inputs.config_cavity_fp32()
+    _say("case cavity256 fp64 on the GPU, 400 steps (reference)")
+    with Lattice(wl, "fp64", check_interval=100) as lat:
+        lat.step(400)
+        return wl, _gpu_fields(lat), lat.nusselt()
+
+
+@pytest.mark.parametrize("prec,tol_u,tol_T,tol_nu", [("fp32", 1e-5, 1e-5, 1e-5), ("fp16", 1e-2, 1e-3, 1e-3)])
+def test_cavity256_reduced_precision_against_fp64_over_400_steps(cavity256_fp64_gpu, prec, tol_u, tol_T, tol_nu):
+    """The measured workload at full size for 400 steps, which the oracle
+    cannot run: FP32 (and FP16 flow storage) against the GPU's FP64 path.
+    Relative global errors of Eq. 52 in u and T and the relative error of
+    Nu_hot: the 1e-5 targets for FP32 (measured about 1e-7), the Nu target of
+    1e-3 for FP16 storage."""
+    wl, ref, nu_ref = cavity256_fp64_gpu
+    _say(f"case cavity256 {prec} vs gpu fp64, 400 steps")
+    with Lattice(wl, prec, check_interval=100) as lat:
+        lat.step(400)
+        fl = _gpu_fields(lat)
+        nu = lat.nusselt()
+    u_g = np.stack([fl["ux"], fl["uy"], fl["uz"]])
+    u_r = np.stack([ref["ux"], ref["uy"], ref["uz"]])
+    e_u = _global_rel(u_g, u_r)
+    e_T = _global_rel(fl["T"] - wl["T_ref"], ref["T"] - wl["T_ref"])
+    e_nu = abs(nu[0] - nu_ref[0]) / abs(nu_ref[0])
+    _say(f"cavity256 {prec}: E(u) {e_u:.3e} E(T) {e_T:.3e} Nu rel {e_nu:.3e} (Nu {nu_ref[0]:.6f}, "
+         f"max|u| {float(np.max(np.abs(u_r))):.3e})")
+    assert e_u <= tol_u and e_T <= tol_T and e_nu <= tol_nu
+
+
 # ---------------------------------------------------------------- open boundaries, FP16 storage
 OPEN_CASES = {
     "q19_inlet_outlet": ((13, 9, 4), 19),
