@@ -109,6 +109,19 @@ def cpu_baseline(workload: dict, steps: int) -> dict:
     }
 
 
+def cpu_baseline_one_thread(steps: int):
+    """The same oracle on one thread (OMP_NUM_THREADS=1), in a child process
+    that starts its own OpenMP runtime; None if it fails."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-only", str(steps)], env=env,
+                           capture_output=True, text=True, timeout=900)
+        return json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        return None
+
+
 def _say(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -364,11 +377,18 @@ def main(argv=None) -> int:
     ap.add_argument("--check-interval", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps on the 256^3 sample (0 skips the CPU baseline)")
+    ap.add_argument("--cpu-steps-one-thread", type=int, default=1,
+                    help="oracle steps on the 256^3 sample on one thread (0 skips them)")
+    ap.add_argument("--oracle-only", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain device-to-device copy timed as the attainable-bandwidth "
                          "reference (0 skips it)")
     args = ap.parse_args(argv)
 
+    if args.oracle_only > 0:
+        import lbm_inputs
+        print(json.dumps(cpu_baseline(lbm_inputs.config_cavity_fp32(), args.oracle_only)), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); there is no "
               "multi-GPU path", file=sys.stderr)
@@ -448,6 +468,11 @@ def main(argv=None) -> int:
     if args.cpu_steps > 0:
         print(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps", file=sys.stderr, flush=True)
         cpu = cpu_baseline(wl, args.cpu_steps)
+        if args.cpu_steps_one_thread > 0:
+            print(f"[bench] cpu baseline: oracle on one thread, {args.cpu_steps_one_thread} steps", file=sys.stderr,
+                  flush=True)
+            one = cpu_baseline_one_thread(args.cpu_steps_one_thread)
+            cpu["one_thread"] = None if one is None else {k: one[k] for k in ("value", "unit", "cores", "sample")}
 
     line = {
         "metric": METRIC,
