@@ -195,9 +195,11 @@ lbm_status lbm_fields(lbm_lattice* h, double* rho, double* ux, double* uy, doubl
 /* Face Nusselt numbers at the current time, FP64, into host nu[6]: for every
  * isothermal face, the mean over the face's nodes of the heat that entered the
  * fluid through it during the last streaming (2 g_k - 2 omega_k sigma T_w for
- * the incoming population k of anti-bounce-back), times L/(alpha_e delta_T):
- * the midpoint rule for Nu_3D of Eqs. 53-55.  0 for other faces.  The hot wall
- * of a cavity reports +Nu, the cold wall -Nu.  Synchronizes. */
+ * the incoming population k of anti-bounce-back, with the wall term 2 omega_k
+ * sigma T_w in the lattice's arithmetic precision, as the step applies it),
+ * times L/(alpha_e delta_T): the midpoint rule for Nu_3D of Eqs. 53-55.  0 for
+ * other faces.  The hot wall of a cavity reports +Nu, the cold wall -Nu.
+ * Synchronizes. */
 lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]);
 
 /* Most recent residual check: r(n) = max(|u(n) - u(n-1)|_2 / |u(n)|_2,
