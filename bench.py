@@ -29,6 +29,10 @@ and with FP16 flow storage side by side, and (unless --cpu-steps 0) their
 errors in u, T and Nu against the FP64 oracle on the 128x32x32 downscale at
 t = 1000 and 2000, the oracle's own run timed as the CPU baseline.
 
+--workload parity32 runs the 32^3 FP64 parity cavity whole (2000 steps) on
+the GPU and with the oracle on the host cores, and reports both times and the
+largest field difference (a cache-resident latency figure, not a roofline).
+
 --workload melting times the enthalpy-based phase-change step (App. B,
 conduction melting of Sec. 4.3) on a 1024x128x128 slab in FP32: 7 populations
 read and written, 56 B per node per step, against the same HBM roofline.
@@ -302,6 +306,76 @@ def bench_channel(args) -> int:
     return 0
 
 
+def bench_parity32(args) -> int:
+    """The 32^3 FP64 parity cavity run whole (2000 steps from the initial state)
+    on the GPU and by the oracle on the host cores, with the largest field
+    difference between the two.  Its 6.8 MB state stays in the caches, so the
+    GPU figure is a latency, not a roofline measurement."""
+    import numpy as np
+    import torch
+
+    import lbm_inputs
+    import oracle
+    from paper_1611_03329_amd import Lattice
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    wl = lbm_inputs.config_cavity_fp64()
+    steps = wl["steps"]
+    lat = Lattice(wl, "fp64", check_interval=args.check_interval)
+    nodes = lat.nodes
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    lat.step(steps)
+    end.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    fl = {k: v.cpu().numpy() for k, v in lat.fields().items()}
+    nu = lat.nusselt()[0]
+    lat.close()
+    _say(f"{wl['name']}: {steps} steps in {ms:.1f} ms on the GPU")
+    with oracle.Oracle(wl) as o:
+        t0 = time.perf_counter()
+        o.step(steps)
+        t1 = time.perf_counter()
+        ref = o.fields()
+        nu_ref = o.nusselt()[0]
+    diff = max(float(np.max(np.abs(fl[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in ref)
+    _say(f"oracle: {t1 - t0:.2f} s; largest field difference {diff:.2e}")
+    line = {
+        "metric": "time to run the FP64 parity cavity (2000 steps)",
+        "value": round(ms / 1e3, 5),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": round(ms / steps, 5),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "porous cavity 32^3, D3Q19 MRT flow + D3Q7 MRT temperature, FP64, phi 0.6, Da 1e-2, "
+                               f"Ra 1e4, Pr 1, seed 1, residual check every {args.check_interval} steps",
+                   "nodes": nodes, "parallelism": "single GPU"},
+        "mlups": round(nodes * steps / (ms / 1e3) / 1e6, 1),
+        "roofline": None,
+        "cache_resident": True,
+        "nu_hot": nu,
+        "max_rel_field_diff_vs_oracle": diff,
+        "nu_rel_diff_vs_oracle": abs(nu - nu_ref) / abs(nu_ref),
+        "cpu_baseline": {"value": round(t1 - t0, 3), "unit": "s", "cores": oracle.threads(), "kind": "oracle",
+                         "sample": "the whole run, 2000 steps of the 32^3 cavity",
+                         "mlups": round(nodes * steps / (t1 - t0) / 1e6, 1)},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_melting(args) -> int:
     """Enthalpy phase-change step (FP32) on a 1024x128x128 melting slab."""
     import torch
@@ -361,7 +435,7 @@ def bench_melting(args) -> int:
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("cavity256", "batched", "served", "channel", "melting"),
+    ap.add_argument("--workload", choices=("cavity256", "batched", "served", "channel", "melting", "parity32"),
                     default="cavity256")
     ap.add_argument("--count", type=int, default=64, help="solves in the batched / served workloads")
     ap.add_argument("--rate", type=float, default=20.0, help="served: mean arrivals per second")
@@ -395,6 +469,8 @@ def main(argv=None) -> int:
         return 2
     if args.workload == "melting":
         return bench_melting(args)
+    if args.workload == "parity32":
+        return bench_parity32(args)
     if args.workload == "channel":
         return bench_channel(args)
     if args.workload != "cavity256":
