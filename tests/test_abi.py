@@ -122,3 +122,27 @@ def test_required_bytes_layout():
     # FP16 storage: 18 moving f in FP16, 6 moving g and 2 rest populations in FP32
     b16 = lbm.required_bytes(lbm.make_params(lbm_inputs.cavity(32), "fp16"))
     assert (18 * 2 + 8 * 4) * n + 4 * n * 4 <= b16 < (18 * 2 + 8 * 4) * n + 4 * n * 4 + (1 << 20)
+
+
+def test_size_limits_are_exact():
+    """Byte offsets inside a population region are 32-bit: a region (the moving
+    flow populations, (q - 1) planes of the node count rounded up to whole
+    tiles of 2048) must stay below 4 GiB, and a box below 2^30 nodes.  The
+    largest FP32 D3Q19 box of this shape is accepted, one more z layer is not;
+    FP16 storage halves the flow region and takes it."""
+    import lbm_inputs
+    from paper_1611_03329_amd import lbm
+    largest = lbm_inputs.cavity((400, 384, 388))       # 59,596,800 nodes: 18 * 4 B * n < 2^32
+    over = lbm_inputs.cavity((400, 384, 389))          # 59,750,400 nodes: 18 * 4 B * n >= 2^32
+    assert 18 * 4 * 400 * 384 * 388 < 1 << 32 <= 18 * 4 * 400 * 384 * 389
+    assert lbm.required_bytes(lbm.make_params(largest, "fp32")) > 26 * 4 * 400 * 384 * 388
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.required_bytes(lbm.make_params(over, "fp32"))
+    assert ei.value.status == 5
+    assert lbm.required_bytes(lbm.make_params(over, "fp16")) > 0
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.required_bytes(lbm.make_params(largest, "fp64"))
+    assert ei.value.status == 5
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.required_bytes(lbm.make_params(lbm_inputs.cavity((1024, 1024, 1025)), "fp16"))
+    assert ei.value.status == 1

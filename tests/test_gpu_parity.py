@@ -301,6 +301,25 @@ def test_cavity256_fp32_two_steps_match_oracle():
         assert err <= 1e-5, (k, err)
 
 
+def test_largest_fp32_box_two_steps_match_oracle():
+    """The largest FP32 D3Q19 box the 32-bit byte offsets allow (400x384x388,
+    59.6 M nodes; its flow-population region is 4 MB short of 4 GiB): one even
+    and one odd step against the oracle, so that no offset near the top of a
+    region wraps."""
+    wl = lbm_inputs.cavity((400, 384, 388), porosity=0.4, darcy=1e-4, rayleigh=1e6, seed=9)
+    _say("case largest fp32 box 400x384x388, 2 steps (oracle on the host)")
+    with oracle.Oracle(wl) as o:
+        o.step(2)
+        ref = o.fields()
+    with Lattice(wl, "fp32", check_interval=100) as lat:
+        lat.step(2)
+        fl = _gpu_fields(lat)
+    errs = _field_errors(fl, ref)
+    _say("largest fp32 box: %s" % {k: "%.2e" % v for k, v in errs.items()})
+    for k, err in errs.items():
+        assert err <= 1e-5, (k, err)
+
+
 @pytest.mark.parametrize("prec,tol_rho,tol_u,tol_T", [("fp32", 1e-5, 1e-5, 1e-5), ("fp16", 2e-4, 5e-3, 1e-5)])
 def test_channel512_two_steps_match_oracle(prec, tol_rho, tol_u, tol_T):
     """The measured channel (512x128x128, D3Q15, inflow, open outlet, heated
