@@ -248,6 +248,45 @@ def test_random_state_fp64_matches_oracle(name):
                 assert abs(h - gr.sum()) <= 1e-11 * max(1.0, abs(h))
 
 
+PARAM_CASES = {
+    "clear_fluid_phi1": dict(porosity=1.0),
+    "brinkman_darcy_no_forchheimer": dict(forchheimer=0.0),
+    "no_buoyancy_ra0": dict(rayleigh=0.0, reynolds=10.0, u_char=0.05),
+    "weak_drag_da1e6": dict(darcy=1e6),
+    "strong_drag_da1e-6": dict(darcy=1e-6),
+    "gravity_x_shifted_tref": dict(gravity_axis=0, T_hot=1.25, T_cold=0.25),
+}
+
+
+@pytest.mark.parametrize("q", [19, 15])
+@pytest.mark.parametrize("name", sorted(PARAM_CASES))
+def test_parameter_limits_fp64_match_oracle(name, q):
+    """The limits of the porous model on a ragged box from a random state:
+    porosity 1, no Forchheimer term (l1 = 0 in the closure of Eq. 28), no
+    buoyancy, Darcy numbers where the drag all but vanishes or dominates, and
+    buoyancy along x with a nonzero reference temperature (shifted thermal
+    populations).  FP64 state against the oracle over steps of both parities."""
+    kw = dict(lattice=q, porosity=0.55, darcy=5e-3, rayleigh=2e5)
+    kw.update(PARAM_CASES[name])
+    wl = lbm_inputs.cavity((9, 6, 5), **kw)
+    wl["faces"] = wl["faces"][:2] + [WALL, WALL, PER, PER]   # isothermal x walls at T_hot, T_cold
+    _say(f"case parameter limit {name} q{q}")
+    with oracle.Oracle(wl) as o:
+        f0, g0 = lbm_inputs.random_state(q, o.shape, 77, amp=0.05, T_amp=0.4)
+        o.set_state(f0, g0)
+        with Lattice(wl, "fp64") as lat:
+            lat.set_state(f0, g0)
+            for n in (1, 1, 4):
+                o.step(n)
+                lat.step(n)
+                fr, gr = o.get_state()
+                f, g = _gpu_state(lat)
+                assert _rel(f, fr) <= 1e-12, (o.time, "f", _rel(f, fr))
+                assert _rel(g, gr) <= 1e-12, (o.time, "g", _rel(g, gr))
+                for k, err in _field_errors(_gpu_fields(lat), o.fields()).items():
+                    assert err <= 1e-11, (o.time, k, err)
+
+
 @pytest.mark.parametrize("q", [19, 15])
 def test_random_state_fp32_matches_oracle(q):
     shape, faces = (17, 16, 15), CASES["q19_walls_moving_lid"][2]
