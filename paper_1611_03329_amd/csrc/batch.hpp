@@ -51,7 +51,7 @@ __device__ __forceinline__ int member_of(const M* __restrict__ mem, int nmem, in
 // block b takes tiles b, b + gridDim.x, ...  A grid smaller than the tile count
 // keeps its blocks resident and lets them walk several tiles (a persistent
 // launch).  With nxcd > 1 the grid is a multiple of nxcd.
-template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
+template <class Lat, class S, class C, bool ODD, int MODE, bool GEN, bool SEP>
 __device__ __forceinline__ void step_tiles(const Member<S, C>* __restrict__ mem, int nmem, int ntiles, int nxcd) {
   int t, end, stride;
   if (nxcd > 1) {
@@ -84,42 +84,50 @@ __device__ __forceinline__ void step_tiles(const Member<S, C>* __restrict__ mem,
     if (lb == 0 && threadIdx.x == 0) gbl(clk)[ODD ? 0 : 1] = now + 1u;
     if constexpr (MODE == kModeCompare) {
       // a member that joined after the last snapshot has nothing to compare yet
-      if (mem[m].check) step_block<Lat, S, C, ODD, kModeCompare, GEN>(kp, sto, snap, part, lb, seed);
-      else step_block<Lat, S, C, ODD, kModePlain, GEN>(kp, sto, snap, part, lb, seed);
+      if (mem[m].check) step_block<Lat, S, C, ODD, kModeCompare, GEN, SEP>(kp, sto, snap, part, lb, seed);
+      else step_block<Lat, S, C, ODD, kModePlain, GEN, SEP>(kp, sto, snap, part, lb, seed);
       // the block reduction's shared slots are reused by the next tile
       __syncthreads();
     } else if constexpr (MODE == kModeSpan) {
       // without a snapshot yet the member only takes one
-      if (mem[m].check) step_block<Lat, S, C, ODD, kModeSpan, GEN>(kp, sto, snap, part, lb, seed);
-      else step_block<Lat, S, C, ODD, kModeSnapshot, GEN>(kp, sto, snap, part, lb, seed);
+      if (mem[m].check) step_block<Lat, S, C, ODD, kModeSpan, GEN, SEP>(kp, sto, snap, part, lb, seed);
+      else step_block<Lat, S, C, ODD, kModeSnapshot, GEN, SEP>(kp, sto, snap, part, lb, seed);
       __syncthreads();
     } else {
-      step_block<Lat, S, C, ODD, MODE, GEN>(kp, sto, snap, part, lb, seed);
+      step_block<Lat, S, C, ODD, MODE, GEN, SEP>(kp, sto, snap, part, lb, seed);
     }
   }
 }
 
+// SEP (separable tiles: the link indices of the odd step from per-axis deltas)
+// is compiled for FP16 storage only, whose step is limited by instruction
+// issue: there it saves 6-7 % of the odd step's vector instructions.  FP32
+// storage is HBM-bound, and the registers the deltas occupy made its step
+// slower.  It is a kernel of its own, not a branch: both address paths in one
+// kernel exceed the register budget below.
+//
 // The step kernel with FP32 arithmetic (FP32 and FP16 storage) is held to 128
 // registers, 4 wavefronts per SIMD: the general wall rules alone would need up
 // to 157 and, sharing the kernel with the lean rules, cut every wavefront's
 // occupancy to 3 (the channel ran 12-18 % slower).  With FP64 arithmetic the
 // same limit would spill heavily, so that kernel keeps its own budget.
-template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
+template <class Lat, class S, class C, bool ODD, int MODE, bool GEN, bool SEP>
 __global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_step(const Member<S, C>* __restrict__ mem, int nmem, int ntiles, int nxcd) {
-  step_tiles<Lat, S, C, ODD, MODE, GEN>(mem, nmem, ntiles, nxcd);
+  step_tiles<Lat, S, C, ODD, MODE, GEN, SEP>(mem, nmem, ntiles, nxcd);
 }
 template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
 __global__ void __launch_bounds__(kMaxBlock) k_step_fp64(const Member<S, C>* __restrict__ mem, int nmem,
                                                          int ntiles, int nxcd) {
-  step_tiles<Lat, S, C, ODD, MODE, GEN>(mem, nmem, ntiles, nxcd);
+  step_tiles<Lat, S, C, ODD, MODE, GEN, false>(mem, nmem, ntiles, nxcd);
 }
 
-// The step kernel for arithmetic type C.
-template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
+// The step kernel for arithmetic type C (SEP: FP16 storage, odd step only).
+template <class Lat, class S, class C, bool ODD, int MODE, bool GEN, bool SEP = false>
 constexpr auto step_kernel() {
+  static_assert(!SEP || (kStochastic<S> && ODD), "separable-tile indices are built for the FP16 odd step only");
   if constexpr (std::is_same<C, double>::value) return &k_step_fp64<Lat, S, C, ODD, MODE, GEN>;
-  else return &k_step<Lat, S, C, ODD, MODE, GEN>;
+  else return &k_step<Lat, S, C, ODD, MODE, GEN, SEP>;
 }
 
 // Block m folds member m's partials of the last compare step and forms its

@@ -200,6 +200,43 @@ __device__ __forceinline__ Nbr make_nbr(const KParams<C>& kp, int x, int y, int 
 
 // Link along velocity e taken with sign SG (+1: to x + e, -1: to x - e):
 // node offset and whether the linked node exists.
+// Separable tiles (kp.sep): when tiles hold whole rows and planes hold whole
+// tiles (or a row holds whole tiles), the element index of moving flow
+// population p at node m splits as fslot(p, m) = X(x) + Y(y) + Z(z) + (p-1)
+// kTile.  A link's target index is then the node's own fslot(1, n) plus one
+// delta per axis it moves along, the same for every population: six deltas
+// per node replace the index arithmetic of each of the 18 (14) links.
+template <class Lat>
+__device__ __forceinline__ void tile_deltas(const Nbr& b, int n, uint32_t f1, int (&td)[3][2]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) td[a][s] = (int)(fslot<Lat>(1, (uint32_t)(n + b.off[a][s])) - f1);
+}
+
+// Index delta and existence of the link along velocity e taken with sign SG,
+// from the per-axis deltas of tile_deltas.
+template <int EX, int EY, int EZ, int SG>
+__device__ __forceinline__ void link_delta(const Nbr& b, const int (&td)[3][2], int& dl, bool& in) {
+  dl = 0;
+  in = true;
+  if constexpr (EX != 0) {
+    constexpr int s = EX * SG > 0 ? 1 : 0;
+    dl += td[0][s];
+    in = in && b.in[0][s];
+  }
+  if constexpr (EY != 0) {
+    constexpr int s = EY * SG > 0 ? 1 : 0;
+    dl += td[1][s];
+    in = in && b.in[1][s];
+  }
+  if constexpr (EZ != 0) {
+    constexpr int s = EZ * SG > 0 ? 1 : 0;
+    dl += td[2][s];
+    in = in && b.in[2][s];
+  }
+}
+
 template <int EX, int EY, int EZ, int SG>
 __device__ __forceinline__ void link(const Nbr& b, int& off, bool& in) {
   off = 0;
@@ -374,15 +411,27 @@ __device__ __forceinline__ void scatter_faces(const KParams<C>& kp, const S& sto
 // (the step that stored it applied the open rule).  The lean rules (periodic
 // faces, static walls, thermal walls) are applied link by link; GEN adds the
 // rules of moving walls and open faces (special faces) as corrections, face by
-// face (gather_walls, scatter_faces).
-template <class Lat, bool ODD, bool GEN, class S, class C>
+// face (gather_walls, scatter_faces).  SEP takes the flow links' indices from
+// tile_deltas (separable tiles only).
+template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false>
 __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                        C (&h)[Lat::Q], C (&p)[7]) {
   h[0] = ld_rs<S, C>(sto, rslot(0, (uint32_t)n));
+  const uint32_t f1 = fslot<Lat>(1, (uint32_t)n);
+  int td[3][2];
+  if constexpr (ODD && SEP) tile_deltas<Lat>(nb, n, f1, td);
   static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     if constexpr (!ODD) {
       h[i] = ld_mf<S, C>(sto, fslot<Lat>(i, (uint32_t)n));
+    } else if constexpr (SEP) {
+      constexpr int io = Lat::opp(i);
+      int dl;
+      bool in;
+      link_delta<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, td, dl, in);
+      const uint32_t e = f1 + (in ? ((uint32_t)(io - 1) << kTileShift) + (uint32_t)dl
+                                  : ((uint32_t)(i - 1) << kTileShift));
+      h[i] = ld_mf<S, C>(sto, e);
     } else {
       constexpr int io = Lat::opp(i);
       int off;
@@ -416,13 +465,16 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n
 // ------------------------------------------------------------------ scatter
 // Post-collision shifted populations of node n, written for the next parity.
 // M holds the node's macroscopic state (used by the open-face rules).
-template <class Lat, bool ODD, bool GEN, class S, class C>
+template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false>
 __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                         const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M, uint32_t seed) {
   st_rs<S, C>(sto, rslot(0, (uint32_t)n), h[0]);
   // random bits for the stochastic FP16 rounding: one xorshift word serves two
   // populations (bits 0-12 and 16-28)
   uint32_t rnd = kStochastic<S> ? (mix32(seed + (uint32_t)n) | 1u) : 0u;
+  const uint32_t f1 = fslot<Lat>(1, (uint32_t)n);
+  int td[3][2];
+  if constexpr (ODD && SEP) tile_deltas<Lat>(nb, n, f1, td);
   static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int io = Lat::opp(i);
@@ -437,6 +489,13 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
     }
     if constexpr (!ODD) {
       st_mf_r<S, C>(sto, fslot<Lat>(io, (uint32_t)n), h[i], r);
+    } else if constexpr (SEP) {
+      int dl;
+      bool in;
+      link_delta<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, td, dl, in);
+      const uint32_t e = f1 + (in ? ((uint32_t)(i - 1) << kTileShift) + (uint32_t)dl
+                                  : ((uint32_t)(io - 1) << kTileShift));
+      st_mf_r<S, C>(sto, e, h[i], r);
     } else {
       int off;
       bool in;
@@ -517,7 +576,7 @@ constexpr int kPartStride = 8;  // doubles per block in the partials buffer
 // The per-node body of a step: gather, moments, residual bookkeeping,
 // collisions, scatter.  G selects the general wall rules; seed (a hash of the
 // lattice's step count) drives the stochastic rounding of FP16 storage.
-template <class Lat, class S, class C, bool ODD, int MODE, bool G>
+template <class Lat, class S, class C, bool ODD, int MODE, bool G, bool SEP = false>
 __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, C* __restrict__ snap, int n,
                                           const Nbr& nb, double (&red)[5], uint32_t seed) {
   C h[Lat::Q], p[7];
@@ -526,7 +585,7 @@ __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, 
   // next wavefronts are in flight sooner (3-4 % faster there; with FP32
   // storage the step is HBM-bound and the same priority costs 1 %)
   if constexpr (kStochastic<S>) __builtin_amdgcn_s_setprio(1);
-  gather<Lat, ODD, G, S, C>(kp, state, n, nb, h, p);
+  gather<Lat, ODD, G, S, C, SEP>(kp, state, n, nb, h, p);
   if constexpr (kStochastic<S>) __builtin_amdgcn_s_setprio(0);
   const Macro<C> M = macro<Lat, C>(kp, h, p);
   LBM_GLOBAL C* sn = gbl(snap);
@@ -550,7 +609,7 @@ __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, 
   }
   collide_flow<Lat, C>(kp, M, h);
   collide_heat<C>(kp, M, p);
-  scatter<Lat, ODD, G, S, C>(kp, state, n, nb, h, p, M, seed);
+  scatter<Lat, ODD, G, S, C, SEP>(kp, state, n, nb, h, p, M, seed);
 }
 
 // Node (x, y, z) lies on a face that moves or is open.
@@ -568,8 +627,10 @@ __device__ __forceinline__ bool on_special_face(const KParams<C>& kp, int x, int
 //   MODE 3 does both: it compares with the snapshot, then replaces it.
 // With GEN the general wall rules run only in wavefronts that hold a node on a
 // moving or open face; every other wavefront takes the lean rules, which give
-// the same result for its nodes.  The choice is uniform per wavefront.
-template <class Lat, class S, class C, bool ODD, int MODE, bool GEN>
+// the same result for its nodes.  The choice is uniform per wavefront.  With
+// SEP (separable tiles, odd step) the lean rules take their link indices from
+// per-axis deltas: the same indices with fewer instructions.
+template <class Lat, class S, class C, bool ODD, int MODE, bool GEN, bool SEP = false>
 __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state, C* __restrict__ snap,
                                            double* __restrict__ part, int lb, uint32_t seed) {
   const int n = lb * blockDim.x + threadIdx.x;
@@ -582,9 +643,9 @@ __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state,
       if (__ballot(on_special_face(kp, x, y, z)) != 0)
         step_node<Lat, S, C, ODD, MODE, true>(kp, state, snap, n, nb, red, seed);
       else
-        step_node<Lat, S, C, ODD, MODE, false>(kp, state, snap, n, nb, red, seed);
+        step_node<Lat, S, C, ODD, MODE, false, SEP && ODD>(kp, state, snap, n, nb, red, seed);
     } else {
-      step_node<Lat, S, C, ODD, MODE, false>(kp, state, snap, n, nb, red, seed);
+      step_node<Lat, S, C, ODD, MODE, false, SEP && ODD>(kp, state, snap, n, nb, red, seed);
     }
   }
   if constexpr (MODE == kModeCompare || MODE == kModeSpan) {

@@ -286,6 +286,9 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
   k->open_heat = 0;
   k->special = 0;
   for (int a = 0; a < 3; ++a) k->per[a] = p->face[2 * a].flow == LBM_FLOW_PERIODIC;
+  // tiles hold whole rows and planes whole tiles (or rows whole tiles): then
+  // tile index and position in the tile split into parts of x, y and z alone
+  k->sep = p->nx % (int)kTile == 0 || ((int)kTile % p->nx == 0 && p->ny % ((int)kTile / p->nx) == 0);
   const double w7 = p->varpi / 6.0;
   for (int f = 0; f < 6; ++f) {
     for (int a = 0; a < 3; ++a) {
@@ -637,30 +640,41 @@ extern "C" lbm_status lbm_derived_params(const lbm_lattice* h, lbm_derived* d) {
 }
 
 // ------------------------------------------------------------------ step
-template <class Lat, class S, class C, bool ODD, bool GEN>
+template <class Lat, class S, class C, bool ODD, bool GEN, bool SEP = false>
 static void launch_step_mode(lbm_lattice* h, const KParams<C>& kp, int mode) {
   const auto* mem = static_cast<const Member<S, C>*>(h->dev_member);
   const dim3 g(h->nblocks), b(h->block);
   if (mode == kModePlain)
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModePlain, GEN>()), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModePlain, GEN, SEP>()), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
   else if (mode == kModeSnapshot)
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeSnapshot, GEN>()), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeSnapshot, GEN, SEP>()), g, b, 0, h->stream, mem, 1, h->nblocks,
+                       0);
   else
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeCompare, GEN>()), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeCompare, GEN, SEP>()), g, b, 0, h->stream, mem, 1, h->nblocks,
+                       0);
 }
 
 // GEN (moving walls or open faces present) selects the kernels that compile
 // those rules; boxes with only periodic faces and static walls use the lean ones.
+// The odd step of an FP16-storage lattice with separable tiles takes the SEP
+// kernel (link indices from per-axis deltas).
 template <class Lat, class S, class C>
 static void launch_step(lbm_lattice* h, const KParams<C>& kp, int mode) {
   const bool gen = kp.moving || kp.open_flow || kp.open_heat;
   if (h->parity == 0) {
     if (gen) launch_step_mode<Lat, S, C, false, true>(h, kp, mode);
     else launch_step_mode<Lat, S, C, false, false>(h, kp, mode);
-  } else {
-    if (gen) launch_step_mode<Lat, S, C, true, true>(h, kp, mode);
-    else launch_step_mode<Lat, S, C, true, false>(h, kp, mode);
+    return;
   }
+  if constexpr (kStochastic<S>) {
+    if (kp.sep) {
+      if (gen) launch_step_mode<Lat, S, C, true, true, true>(h, kp, mode);
+      else launch_step_mode<Lat, S, C, true, false, true>(h, kp, mode);
+      return;
+    }
+  }
+  if (gen) launch_step_mode<Lat, S, C, true, true>(h, kp, mode);
+  else launch_step_mode<Lat, S, C, true, false>(h, kp, mode);
 }
 
 extern "C" lbm_status lbm_step(lbm_lattice* h, int64_t nsteps) {
@@ -929,7 +943,9 @@ extern "C" lbm_status lbm_transfer_state(lbm_lattice* dst, lbm_lattice* src) {
 // A batch advances its member lattices together.  Members share the lattice
 // type, precision, stream and time parity.  They are packed, in join order,
 // into launch groups: members with the lean wall rules and members with the
-// general ones never share a group, and with a group size limit G > 0 a group
+// general ones never share a group (nor, with FP16 storage, members with and
+// without separable tiles, whose odd steps take different kernels), and with a
+// group size limit G > 0 a group
 // holds members whose states add up to at most G bytes (one larger member
 // forms a group of its own).  One kernel launch advances one group by one step.
 //
@@ -964,6 +980,7 @@ struct lbm_batch {
   std::vector<int> fresh;             // a result row not yet pulled into the member
   struct Group {
     int gen, first, count, tiles;
+    int sep;  // FP16 storage with separable tiles: the odd step takes the SEP kernel
   };
   std::vector<Group> groups;
   std::vector<int> slot;  // member index -> its row in the member table and in out
@@ -983,6 +1000,12 @@ struct lbm_batch {
 
 static bool member_general(const lbm_lattice* h) {
   return h->kd.moving || h->kd.open_flow || h->kd.open_heat;
+}
+
+// Launch variant of member h: bit 0 the general wall rules, bit 1 separable
+// tiles with FP16 storage (its odd step takes the SEP kernel).
+static int member_variant(const lbm_lattice* h) {
+  return (member_general(h) ? 1 : 0) | (h->prec == LBM_FP16_STORAGE && h->kf.sep ? 2 : 0);
 }
 
 // Bytes of populations a step streams for member h.
@@ -1038,16 +1061,17 @@ static lbm_status batch_upload_typed(lbm_batch* b) {
   std::vector<Member<S, C>> table;
   b->groups.clear();
   b->slot.assign(b->members.size(), 0);
-  for (int gen = 0; gen < 2; ++gen) {
-    lbm_batch::Group cur{gen, (int)table.size(), 0, 0};
+  for (int var = 0; var < 4; ++var) {
+    const int gen = var & 1, sep = var >> 1;
+    lbm_batch::Group cur{gen, (int)table.size(), 0, 0, sep};
     uint64_t bytes = 0;
     for (size_t i = 0; i < b->members.size(); ++i) {
       lbm_lattice* h = b->members[i];
-      if ((int)member_general(h) != gen) continue;
+      if (member_variant(h) != var) continue;
       const uint64_t mb = member_state_bytes(h);
       if (cur.count > 0 && b->group_bytes > 0 && bytes + mb > b->group_bytes) {
         b->groups.push_back(cur);
-        cur = lbm_batch::Group{gen, (int)table.size(), 0, 0};
+        cur = lbm_batch::Group{gen, (int)table.size(), 0, 0, sep};
         bytes = 0;
       }
       Member<S, C> m;
@@ -1107,7 +1131,7 @@ static lbm_status batch_upload_typed(lbm_batch* b) {
   // valid while the buffers, the groups and the launch shape are unchanged
   std::vector<int64_t> k = {(int64_t)(uintptr_t)b->dev_mem, (int64_t)(uintptr_t)b->dev_out,
                             (int64_t)(uintptr_t)b->host_out, b->block, b->per_cu, b->check, b->nxcd};
-  for (const auto& g : b->groups) k.insert(k.end(), {g.gen, g.first, g.count, g.tiles});
+  for (const auto& g : b->groups) k.insert(k.end(), {g.gen, g.first, g.count, g.tiles, g.sep});
   if (k != b->key) batch_drop_graphs(b);
   b->key = k;
   return LBM_OK;
@@ -1148,6 +1172,17 @@ template <class Lat, class S, class C, bool ODD, int MODE>
 static void batch_launch_mode(const lbm_batch* b, const lbm_batch::Group& g) {
   const auto* mem = static_cast<const Member<S, C>*>(b->dev_mem) + g.first;
   const int grid = batch_grid(b, g.tiles);
+  if constexpr (kStochastic<S> && ODD) {
+    if (g.sep) {
+      if (g.gen)
+        hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, true, true>()), dim3(grid), dim3(b->block), 0, b->stream,
+                           mem, g.count, g.tiles, b->nxcd);
+      else
+        hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, false, true>()), dim3(grid), dim3(b->block), 0,
+                           b->stream, mem, g.count, g.tiles, b->nxcd);
+      return;
+    }
+  }
   if (g.gen)
     hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, true>()), dim3(grid), dim3(b->block), 0, b->stream, mem, g.count,
                        g.tiles, b->nxcd);

@@ -28,6 +28,7 @@ struct KParams {
   int open_flow;    // bit f set: face f is an open outlet for f (flow)
   int open_heat;    // bit f set: face f is an outflow face for g
   int special;      // bit f set: face f moves or is open (its nodes need the general rules)
+  int sep;          // the tiled element index is a sum of an x, a y and a z part (see tile_deltas)
   C u_wall[6][3];   // wall velocity per face
   C heat_a[6];      // thermal wall rule: p_in = heat_a * p_out + heat_b (1, 0 on outflow faces)
   C heat_b[6];

@@ -33,9 +33,10 @@ def _say(msg):
 
 
 def _members():
-    """Five D3Q19 workloads: three with the lean wall rules (static walls,
-    periodic faces), two with the general ones (a moving lid; an inlet and an
-    open outlet).  Name -> (workload, random-state seed or None)."""
+    """Seven D3Q19 workloads: four with the lean wall rules (static walls,
+    periodic faces), three with the general ones (a moving lid; an inlet and
+    an open outlet, twice); two of them have separable tiles.  Name ->
+    (workload, random-state seed or None)."""
     lid = lbm_inputs.cavity((13, 7, 5), porosity=0.55, darcy=5e-3, rayleigh=2e5)
     lid["faces"] = [face("wall", "isothermal", 0.5), face("wall", "isothermal", -0.5), WALL, WALL,
                     WALL, face("wall", "adiabatic", 0.0, (0.02, -0.01, 0.0))]
@@ -46,6 +47,11 @@ def _members():
         "lid": (lid, 11),
         "perx": (perx, 12),
         "channel": (lbm_inputs.channel((16, 8, 6), lattice=19), None),
+        # separable tiles (64 divides the 2048-node tile, 32 rows per tile divide
+        # ny): in FP16 mode these take the odd-step kernel with per-axis link
+        # deltas, a launch group of their own
+        "sep": (lbm_inputs.cavity((64, 32, 3), rayleigh=1e5, seed=8), 13),
+        "sepchan": (lbm_inputs.channel((64, 32, 4), lattice=19), None),
         # more tiles than a persistent grid of 1 block/CU at 256 threads or
         # 4 blocks/CU at 64 threads has blocks: those blocks take several tiles
         "big": (lbm_inputs.cavity((48, 47, 49), rayleigh=1e5, seed=6), None),
