@@ -580,13 +580,15 @@ template <class Lat, class S, class C, bool ODD, int MODE, bool G, bool SEP = fa
 __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, C* __restrict__ snap, int n,
                                           const Nbr& nb, double (&red)[5], uint32_t seed) {
   C h[Lat::Q], p[7];
-  // FP16 storage makes the step issue-bound: a wavefront that is issuing its
-  // loads goes before wavefronts that are computing, so the loads of the
-  // next wavefronts are in flight sooner (3-4 % faster there; with FP32
-  // storage the step is HBM-bound and the same priority costs 1 %)
-  if constexpr (kStochastic<S>) __builtin_amdgcn_s_setprio(1);
+  // A wavefront that is issuing its loads goes before wavefronts that are
+  // computing, so the loads of the next wavefronts are in flight sooner.
+  // Measured: FP16 storage (issue-bound) 3-4 % faster; FP32 storage 0.7-0.9 %
+  // faster in the even step but 1.5 % slower in the odd step, whose loads
+  // reach neighbour tiles; FP64 keeps the default.
+  constexpr bool kLoadPriority = kStochastic<S> || (!ODD && std::is_same<C, float>::value);
+  if constexpr (kLoadPriority) __builtin_amdgcn_s_setprio(1);
   gather<Lat, ODD, G, S, C, SEP>(kp, state, n, nb, h, p);
-  if constexpr (kStochastic<S>) __builtin_amdgcn_s_setprio(0);
+  if constexpr (kLoadPriority) __builtin_amdgcn_s_setprio(0);
   const Macro<C> M = macro<Lat, C>(kp, h, p);
   LBM_GLOBAL C* sn = gbl(snap);
   if constexpr (MODE == kModeCompare || MODE == kModeSpan) {
