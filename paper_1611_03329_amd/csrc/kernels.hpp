@@ -582,10 +582,11 @@ __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, 
   C h[Lat::Q], p[7];
   // A wavefront that is issuing its loads goes before wavefronts that are
   // computing, so the loads of the next wavefronts are in flight sooner.
-  // Measured: FP16 storage (issue-bound) 3-4 % faster; FP32 storage 0.7-0.9 %
-  // faster in the even step but 1.5 % slower in the odd step, whose loads
-  // reach neighbour tiles; FP64 keeps the default.
-  constexpr bool kLoadPriority = kStochastic<S> || (!ODD && std::is_same<C, float>::value);
+  // Measured: FP16 storage (issue-bound) 3-4 % faster; FP64 (2-3 wavefronts
+  // per SIMD) 0.8-0.9 % faster; FP32 storage 0.7-0.9 % faster in the even
+  // step but 1.5 % slower in the odd step, whose loads reach neighbour tiles.
+  constexpr bool kLoadPriority =
+      kStochastic<S> || std::is_same<C, double>::value || (!ODD && std::is_same<C, float>::value);
   if constexpr (kLoadPriority) __builtin_amdgcn_s_setprio(1);
   gather<Lat, ODD, G, S, C, SEP>(kp, state, n, nb, h, p);
   if constexpr (kLoadPriority) __builtin_amdgcn_s_setprio(0);
