@@ -134,7 +134,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_step_enthalpy(const KParams<C> kp
   node_coords(kp, n, x, y, z);
   const Nbr nb = make_nbr(kp, x, y, z);
   C g[7];
+  // FP64: loads issued at raised wavefront priority (1.6 % faster; FP32 unchanged)
+  if constexpr (std::is_same<C, double>::value) __builtin_amdgcn_s_setprio(1);
   gather_g<ODD, S, C>(kp, sto, n, nb, g);
+  if constexpr (std::is_same<C, double>::value) __builtin_amdgcn_s_setprio(0);
   collide_enthalpy<C>(ec, g);
   scatter_g<ODD, S, C>(kp, sto, n, nb, g);
 }
