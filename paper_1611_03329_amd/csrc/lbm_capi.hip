@@ -1518,20 +1518,19 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
   const int blocks_c[] = {64, 128, 256};
   const int per_cu_c[] = {0, 4, 8};
   float best = -1.0f, ms = 0.0f;
+  // group size and tile order together: which order is faster depends on
+  // how much of a group the last-level cache holds
   for (uint64_t g : groups_c) {
-    lbm_launch c = cur;
-    c.group_bytes = g;
-    if ((st_ = trial(c, &ms)) != LBM_OK) break;
-    if (best < 0.0f || ms < best) best = ms, cur.group_bytes = g;
+    for (int x : xcd_c) {
+      lbm_launch c = cur;
+      c.group_bytes = g;
+      c.xcd_ranges = x;
+      if ((st_ = trial(c, &ms)) != LBM_OK) break;
+      if (best < 0.0f || ms < best) best = ms, cur.group_bytes = g, cur.xcd_ranges = x;
+    }
+    if (st_ != LBM_OK) break;
   }
   const lbm_launch start = cur;  // measured already
-  for (int x : xcd_c) {
-    if (st_ != LBM_OK || x == start.xcd_ranges) continue;
-    lbm_launch c = cur;
-    c.xcd_ranges = x;
-    if ((st_ = trial(c, &ms)) != LBM_OK) break;
-    if (ms < best) best = ms, cur.xcd_ranges = x;
-  }
   for (int bl : blocks_c) {
     if (st_ != LBM_OK || bl == start.block) continue;
     lbm_launch c = cur;

@@ -276,7 +276,7 @@ def test_autotune_keeps_results():
         assert group in [0] + [m * MiB for m in (8, 16, 32, 64, 128, 256, 512)]
         b.step(4)
         steps = mem["cavity"].time
-        assert steps == 13 * 2 * 10 + 4   # 13 candidates, one untimed and one timed interval each
+        assert steps == 20 * 2 * 10 + 4   # 16 group/order pairs + 2 tile sizes + 2 grids, two intervals each
         for k, (w, s) in ms.items():
             ref = _make(w, s, "fp32", 0)
             ref.step(steps)
