@@ -631,8 +631,8 @@ __device__ __forceinline__ bool on_special_face(const KParams<C>& kp, int x, int
 // With GEN the general wall rules run only in wavefronts that hold a node on a
 // moving or open face; every other wavefront takes the lean rules, which give
 // the same result for its nodes.  The choice is uniform per wavefront.  With
-// SEP (separable tiles, odd step) the lean rules take their link indices from
-// per-axis deltas: the same indices with fewer instructions.
+// SEP (separable tiles, odd step) both take their link indices from per-axis
+// deltas: the same indices with fewer instructions.
 template <class Lat, class S, class C, bool ODD, int MODE, bool GEN, bool SEP = false>
 __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state, C* __restrict__ snap,
                                            double* __restrict__ part, int lb, uint32_t seed) {
@@ -644,7 +644,7 @@ __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state,
     const Nbr nb = make_nbr(kp, x, y, z);
     if constexpr (GEN) {
       if (__ballot(on_special_face(kp, x, y, z)) != 0)
-        step_node<Lat, S, C, ODD, MODE, true>(kp, state, snap, n, nb, red, seed);
+        step_node<Lat, S, C, ODD, MODE, true, SEP && ODD>(kp, state, snap, n, nb, red, seed);
       else
         step_node<Lat, S, C, ODD, MODE, false, SEP && ODD>(kp, state, snap, n, nb, red, seed);
     } else {
