@@ -81,11 +81,12 @@ def traffic_from_profiles(nodes: int):
     return rec.get("bytes_per_launch")
 
 
-def valu_from_profiles(nodes: int, precision: str):
+def valu_from_profiles(nodes: int, stem: str):
     """Wave-level VALU instructions per step of the whole lattice (mean of the
-    two parities' step kernels) from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"step_cavity256_{precision}_valu.json")
+    two parities' step kernels) from the committed rocprofv3 counter summary
+    profiles/<stem>_valu.json, if it was taken on the current kernel source;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"{stem}_valu.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -250,6 +251,12 @@ def bench_channel(args) -> int:
         runs[prec] = {"ms_per_step": round(ms, 5), "mlups": round(nodes / (ms / 1e3) / 1e6, 1),
                       "bytes_per_node": bpn, "achieved_GBps": round(gbps, 1),
                       "frac": round(gbps / PEAK_HBM_GBPS, 4)}
+        if prec == "fp16":
+            # FP16 mode is limited by instruction issue: its VALU issue rate
+            valu = valu_from_profiles(nodes, "step_channel512x128x128_fp16")
+            runs[prec]["valu_issue"] = None if valu is None else {
+                "wave_instructions_per_step": valu,
+                "per_cu_per_clock": round(valu / (ms / 1e3) / PEAK_VALU_WAVE_INSTR_PER_S, 4)}
         _say(f"{wl['name']} {prec}: {ms:.4f} ms/step, {runs[prec]['mlups']} MLUPS, {gbps:.0f} GB/s")
 
     accuracy, cpu = None, None
@@ -535,7 +542,7 @@ def main(argv=None) -> int:
     if fp16:
         # FP16 mode issues more vector instructions per node than the HBM time
         # of its 136 bytes covers: report the issue rate beside the bytes
-        valu = valu_from_profiles(nodes, "fp16")
+        valu = valu_from_profiles(nodes, "step_cavity256_fp16")
         roofline["valu_issue"] = None if valu is None else {
             "wave_instructions_per_step": valu,
             "per_cu_per_clock": round(valu / (ms_per_step / 1e3) / PEAK_VALU_WAVE_INSTR_PER_S, 4)}

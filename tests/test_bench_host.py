@@ -29,11 +29,12 @@ def test_the_valu_profile_names_the_kernel_it_was_taken_on():
     """The FP16-mode instruction counts the bench line reads carry the same
     kernel hash as the traffic profile and lie between the static counts of
     the two parities' kernels' lean paths (about 600 to 1200 per wavefront)."""
-    with open(os.path.join(ROOT, "profiles", "step_cavity256_fp16_valu.json")) as f:
-        rec = json.load(f)
     with open(os.path.join(ROOT, "profiles", "step_cavity256_fp32_traffic.json")) as f:
         traffic = json.load(f)
-    assert rec["kernel_hash"] == traffic["kernel_hash"]
-    waves = rec["nodes"] // 64
-    assert 600 <= rec["even_valu"] / waves < rec["odd_valu"] / waves <= 1200
-    assert rec["valu_per_step"] == (rec["even_valu"] + rec["odd_valu"]) / 2
+    for stem in ("step_cavity256_fp16", "step_channel512x128x128_fp16"):
+        with open(os.path.join(ROOT, "profiles", f"{stem}_valu.json")) as f:
+            rec = json.load(f)
+        assert rec["kernel_hash"] == traffic["kernel_hash"]
+        waves = rec["nodes"] // 64
+        assert 600 <= rec["even_valu"] / waves < rec["odd_valu"] / waves <= 1200
+        assert rec["valu_per_step"] == (rec["even_valu"] + rec["odd_valu"]) / 2
