@@ -25,7 +25,8 @@ a resident-node cap (FP32).
 
 --workload channel times the 512x128x128 porous channel (D3Q15 flow + D3Q7
 temperature, inflow, open outlet, heated and cooled walls) with FP32 storage
-and with FP16 flow storage side by side, and (unless --cpu-steps 0) their
+and with FP16 flow storage side by side (FP16 mode with its VALU issue rate,
+as above), and (unless --cpu-steps 0) their
 errors in u, T and Nu against the FP64 oracle on the 128x32x32 downscale at
 t = 1000 and 2000, the oracle's own run timed as the CPU baseline.
 
