@@ -60,6 +60,7 @@ class Result:
     unstable: bool = False
     nu: tuple = ()          # face Nusselt numbers at retirement
     promoted_at: int = -1   # steps taken in FP16 storage before the move to FP32
+    fields: dict | None = None  # rho, ux, uy, uz, T at retirement (host arrays), if kept
 
     @property
     def latency(self) -> float:
@@ -110,7 +111,7 @@ class Server:
     def __init__(self, precision: str = "fp32", check_interval: int = 100, tol: float = 1e-6,
                  max_steps: int = 200_000, hbm_budget: int | None = None, max_members: int = 256,
                  graph: bool = True, launch: tuple | None = None, plateau: tuple = (0.9, 5), device=None,
-                 policy: str = "fcfs", max_nodes: int | None = None):
+                 policy: str = "fcfs", max_nodes: int | None = None, keep_fields: bool = False):
         if check_interval <= 0 or check_interval % 2:
             raise ValueError("check_interval must be a positive even number (chunks keep the parity)")
         if precision not in ("fp32", "fp16"):
@@ -118,6 +119,8 @@ class Server:
         if policy not in ("fcfs", "smallest"):
             raise ValueError("policy must be fcfs or smallest")
         self.policy = policy
+        # keep every retired solve's final fields (host copies) in its Result
+        self.keep_fields = bool(keep_fields)
         # cap on the nodes resident at once (None: only the HBM budget limits);
         # a request larger than the cap still runs, alone
         self.max_nodes = None if max_nodes is None else int(max_nodes)
@@ -184,6 +187,8 @@ class Server:
             res = e["res"]
             if not res.unstable:
                 res.nu = tuple(lat.nusselt())
+                if self.keep_fields:
+                    res.fields = {k: v.cpu().numpy() for k, v in lat.fields().items()}
             res.finished = clock() - t0
             lat.close()
             del active[id(lat)]
@@ -322,21 +327,27 @@ def solve_sequential(requests: list, precision: str = "fp32", check_interval: in
 
 
 def summarize(results: list) -> dict:
-    """p50/p99 time to converge, solves/s and aggregate MLUPS of one run."""
+    """One run's figures.  Throughput and time to converge count the converged
+    solves only (a solve stopped at the step cap or found unstable is no
+    solve); their numbers are reported beside.  p50/p99 are taken over the
+    converged solves' times from arrival to retirement, solves/s is converged
+    solves over the makespan (first arrival to last retirement of any
+    request), and MLUPS counts the node updates of every request."""
     import numpy as np
     fin = [r for r in results if not math.isnan(r.finished)]
-    lat = np.array([r.latency for r in fin])
+    conv = [r for r in fin if r.converged]
+    lat = np.array([r.latency for r in conv])
     span = max(r.finished for r in fin) - min(r.arrival for r in fin) if fin else math.nan
     node_steps = sum(r.nodes * r.steps for r in fin)
     return {
         "requests": len(results),
-        "converged": sum(r.converged for r in results),
+        "converged": len(conv),
         "unstable": sum(r.unstable for r in results),
         "capped": sum((not r.converged) and (not r.unstable) for r in results),
         "p50_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
         "p99_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
         "makespan_s": span,
-        "solves_per_s": len(fin) / span if span > 0 else math.nan,
+        "solves_per_s": len(conv) / span if span > 0 else math.nan,
         "mlups": node_steps / span / 1e6 if span > 0 else math.nan,
         "steps_total": int(sum(r.steps for r in fin)),
     }

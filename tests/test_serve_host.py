@@ -32,6 +32,24 @@ def test_requests_sorted_by_arrival_and_summary():
     assert isinstance(Request(0, 0.0, {}), Request)
 
 
+def test_capped_solves_are_not_counted_as_solves():
+    """A solve stopped at the step cap (or unstable) counts in `capped`
+    (`unstable`), not in solves/s nor in the time-to-converge percentiles; its
+    node updates still count in MLUPS."""
+    res = []
+    for i in range(4):
+        r = Result(i, "", 1000, arrival=0.0, finished=1.0 + i, steps=100)
+        r.converged = i < 2
+        r.unstable = i == 3
+        res.append(r)
+    s = summarize(res)
+    assert (s["converged"], s["capped"], s["unstable"]) == (2, 1, 1)
+    assert abs(s["makespan_s"] - 4.0) < 1e-12
+    assert abs(s["solves_per_s"] - 2 / 4.0) < 1e-12
+    assert abs(s["p99_s"] - (1.0 + 0.99)) < 1e-12          # over the converged latencies 1 and 2
+    assert abs(s["mlups"] - 4 * 1000 * 100 / 4.0 / 1e6) < 1e-12
+
+
 def test_admission_policies():
     """First come first served admits only the head of the queue; smallest
     first takes the fitting request with the fewest nodes; a node cap holds
