@@ -37,6 +37,17 @@
  * Functions documented as "asynchronous" return after enqueueing; functions
  * that return host values synchronize that stream.
  *
+ * Caller buffers of fields and states (lbm_fields, lbm_get_state,
+ * lbm_set_state, lbm_enthalpy_fields) may be device memory of the lattice's
+ * device (the device current at lbm_create; managed memory counts as device
+ * memory) or host memory, pinned or pageable.  Each pointer is classified with
+ * hipPointerGetAttributes before any launch: device buffers are read or
+ * written by the kernels directly and the call stays asynchronous; host
+ * buffers go through a device staging buffer the call allocates and frees,
+ * with a stream-ordered copy, and the call then synchronizes the lattice's
+ * stream before it returns.  Memory of another device, or of a kind that is
+ * neither, gives LBM_ERR_INVALID_ARG with nothing enqueued.
+ *
  * Errors: every function returns an lbm_status; LBM_OK is 0.  On an error the
  * lattice is unchanged unless stated; lbm_last_error() returns a thread-local
  * message describing the last failure on the calling thread.
@@ -161,10 +172,12 @@ lbm_status lbm_required_bytes(const lbm_params* p, size_t* bytes);
 
 /* Creates a lattice and enqueues its initialisation (f = f^eq(rho0, init_u) of
  * Eq. 24/18, g = g^eq(T_init, init_u) of Eq. 42) on `stream` (a hipStream_t; NULL = null stream).
- * dev_buf: caller-owned device memory of at least lbm_required_bytes() bytes,
- * 256-byte aligned, kept alive until lbm_destroy; or NULL, in which case the
- * library allocates (and later frees) it.  Parameters are validated before any
- * allocation or device work.  Asynchronous. */
+ * dev_buf: caller-owned device memory of the current device, at least
+ * lbm_required_bytes() bytes, 256-byte aligned, kept alive until lbm_destroy;
+ * or NULL, in which case the library allocates (and later frees) it.  Host
+ * memory or memory of another device is refused (LBM_ERR_INVALID_ARG).
+ * Parameters are validated before any allocation or device work.  The
+ * lattice lives on the current device; call it with that device current. */
 lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t bytes, void* stream,
                       lbm_lattice** out);
 
@@ -188,8 +201,9 @@ lbm_status lbm_time(const lbm_lattice* h, int64_t* t);
 lbm_status lbm_derived_params(const lbm_lattice* h, lbm_derived* d);
 
 /* Writes rho (Eq. 25), u (Eqs. 27-28) and T (Eq. 39) at the current time into
- * caller-owned DEVICE buffers of nx*ny*nz FP64 values each, x fastest.  Any
- * pointer may be NULL to skip that field.  Asynchronous. */
+ * caller-owned buffers (device or host memory, see "Caller buffers" above) of
+ * nx*ny*nz FP64 values each, x fastest.  Any pointer may be NULL to skip that
+ * field.  Asynchronous for device buffers; synchronizes when one is host memory. */
 lbm_status lbm_fields(lbm_lattice* h, double* rho, double* ux, double* uy, double* uz, double* T);
 
 /* Face Nusselt numbers at the current time, FP64, into host nu[6]: for every
@@ -214,24 +228,28 @@ lbm_status lbm_residual(lbm_lattice* h, double* r, int64_t* at_step);
  * deterministic).  Synchronizes. */
 lbm_status lbm_totals(lbm_lattice* h, double* mass, double* heat);
 
-/* Copies the pre-collision state at the current time into caller-owned DEVICE
- * buffers, FP64, layout [q][z][y][x] for f (q = 19 or 15) and [7][z][y][x] for g.
- * Either pointer may be NULL.  Asynchronous. */
+/* Copies the pre-collision state at the current time into caller-owned buffers
+ * (device or host memory), FP64, layout [q][z][y][x] for f (q = 19 or 15) and
+ * [7][z][y][x] for g.  Either pointer may be NULL.  Asynchronous for device
+ * buffers; synchronizes when one is host memory. */
 lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g);
 
-/* Replaces the state with caller-given DEVICE FP64 arrays (same layout as
- * lbm_get_state; both required), rounding to the storage precision.  The time
- * counter is kept; the pending residual snapshot is discarded.  Asynchronous. */
+/* Replaces the state with caller-given FP64 arrays in device or host memory
+ * (same layout as lbm_get_state; both required), rounding to the storage
+ * precision.  The time counter is kept; the pending residual snapshot is
+ * discarded.  Asynchronous for device arrays (keep them unchanged until the
+ * stream has passed the copy); synchronizes when one is host memory. */
 lbm_status lbm_set_state(lbm_lattice* h, const double* f, const double* g);
 
 /* Enthalpy lattices (energy = LBM_ENERGY_ENTHALPY): temperature (Eq. B8), effective
  * enthalpy (Eq. B7) and liquid fraction (Eq. B9) at the current time into
- * caller-owned DEVICE buffers of nx*ny*nz FP64 values, x fastest; any pointer may
- * be NULL.  The heat capacity ratios of Eq. B4 are sigma_l = phi + (1 - phi)
+ * caller-owned buffers (device or host memory) of nx*ny*nz FP64 values, x
+ * fastest; any pointer may be NULL.  The heat capacity ratios of Eq. B4 are sigma_l = phi + (1 - phi)
  * matrix_heat and sigma_s = phi c_ps / c_pl + (1 - phi) matrix_heat, c_p,ref is
  * the harmonic mean of c_pl and c_ps (Eq. B13) and the liquidus enthalpy is
  * sigma_l c_pl T_l + phi L_a.  Walls: anti-bounce-back at T_w with the weight
- * varpi c_p,ref / 6 of Eq. B12, bounce-back at adiabatic walls.  Asynchronous.
+ * varpi c_p,ref / 6 of Eq. B12, bounce-back at adiabatic walls.  Asynchronous
+ * for device buffers; synchronizes when one is host memory.
  * LBM_ERR_UNSUPPORTED for a temperature lattice; conversely lbm_fields,
  * lbm_nusselt, lbm_totals, lbm_transfer_state and batches refuse enthalpy
  * lattices, and their lbm_get_state / lbm_set_state take f = NULL. */

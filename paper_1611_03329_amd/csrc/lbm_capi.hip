@@ -48,6 +48,7 @@ struct lbm_lattice {
   lbm_params p;
   lbm_derived d;
   hipStream_t stream = nullptr;
+  int device = 0;  // the device current at creation: the lattice's memory lives there
   void* buf = nullptr;
   bool owns_buf = false;
   size_t bytes = 0;
@@ -476,6 +477,115 @@ static lbm_status launch_check(const char* what) {
   return LBM_OK;
 }
 
+// ------------------------------------------------------------------ caller buffers
+// Where a caller's buffer lives decides how a kernel reaches it.  Device memory
+// (and managed memory) of the lattice's device is handed to the kernels as it
+// is.  Host memory, pinned or pageable, goes through a device staging buffer
+// and a stream-ordered copy.  Anything else (memory of another device, an
+// array object) is refused before any launch.
+enum class MemKind { Device, Host };
+
+static lbm_status classify(const void* p, int device, const char* what, MemKind* kind) {
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof a);
+  const hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e == hipErrorInvalidValue || (e == hipSuccess && a.type == hipMemoryTypeUnregistered)) {
+    (void)hipGetLastError();  // a failed query leaves its error behind for the next call
+    *kind = MemKind::Host;    // memory HIP does not know: ordinary host memory
+    return LBM_OK;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LBM_ERR_DEVICE, "hipPointerGetAttributes(%s) failed: %s", what, hipGetErrorString(e));
+  }
+  if (a.type == hipMemoryTypeHost) {
+    *kind = MemKind::Host;
+    return LBM_OK;
+  }
+  if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) {
+    if (a.device != device)
+      return fail(LBM_ERR_INVALID_ARG, "%s is memory of device %d; the lattice lives on device %d", what, a.device,
+                  device);
+    *kind = MemKind::Device;
+    return LBM_OK;
+  }
+  return fail(LBM_ERR_INVALID_ARG, "%s is neither device nor host memory (memory type %d)", what, (int)a.type);
+}
+
+// The caller buffers of one call.  resolve() classifies each non-NULL buffer;
+// host buffers get slices of one device staging allocation, so that dev[i] is
+// what the kernels read or write.  from_host() enqueues the input copies before
+// the kernels, to_host() the output copies after them; finish() waits for the
+// stream and frees the staging memory (also on error paths, via the destructor).
+struct Staging {
+  static constexpr int kMax = 5;
+  hipStream_t stream = nullptr;
+  int n = 0;
+  void* user[kMax] = {};
+  void* dev[kMax] = {};
+  size_t bytes[kMax] = {};
+  bool host[kMax] = {};
+  void* buf = nullptr;
+
+  explicit Staging(hipStream_t s) : stream(s) {}
+  Staging(const Staging&) = delete;
+  Staging& operator=(const Staging&) = delete;
+  ~Staging() {
+    if (buf) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipFree(buf);
+    }
+  }
+  lbm_status resolve(int device, const void* const* ptrs, const size_t* sizes, const char* const* names, int count) {
+    n = count;
+    size_t total = 0;
+    size_t off[kMax] = {};
+    for (int i = 0; i < n; ++i) {
+      user[i] = const_cast<void*>(ptrs[i]);
+      bytes[i] = sizes[i];
+      host[i] = false;
+      dev[i] = user[i];
+      if (!user[i]) continue;
+      MemKind k;
+      lbm_status st = classify(user[i], device, names[i], &k);
+      if (st != LBM_OK) return st;
+      if (k == MemKind::Host) {
+        host[i] = true;
+        off[i] = total;
+        total += align_up(bytes[i], 256);
+      }
+    }
+    if (total) {
+      hipError_t e = hipMalloc(&buf, total);
+      if (e != hipSuccess) {
+        buf = nullptr;
+        return fail(LBM_ERR_OUT_OF_MEMORY, "staging buffer of %zu bytes for host memory: %s", total,
+                    hipGetErrorString(e));
+      }
+      for (int i = 0; i < n; ++i)
+        if (host[i]) dev[i] = static_cast<char*>(buf) + off[i];
+    }
+    return LBM_OK;
+  }
+  lbm_status from_host() {
+    for (int i = 0; i < n; ++i)
+      if (host[i]) HIP_TRY(hipMemcpyAsync(dev[i], user[i], bytes[i], hipMemcpyHostToDevice, stream));
+    return LBM_OK;
+  }
+  lbm_status to_host() {
+    for (int i = 0; i < n; ++i)
+      if (host[i]) HIP_TRY(hipMemcpyAsync(user[i], dev[i], bytes[i], hipMemcpyDeviceToHost, stream));
+    return LBM_OK;
+  }
+  lbm_status finish() {
+    if (!buf) return LBM_OK;
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipFree(buf));
+    buf = nullptr;
+    return LBM_OK;
+  }
+};
+
 extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t bytes, void* stream,
                                  lbm_lattice** out) {
   if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
@@ -490,11 +600,21 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
     if ((reinterpret_cast<uintptr_t>(dev_buf) & 255) != 0)
       return fail(LBM_ERR_INVALID_ARG, "device buffer must be 256-byte aligned");
   }
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  if (dev_buf) {
+    // the state is streamed by every step: it must be device memory
+    MemKind k;
+    lbm_status sk = classify(dev_buf, device, "dev_buf", &k);
+    if (sk != LBM_OK) return sk;
+    if (k != MemKind::Device) return fail(LBM_ERR_INVALID_ARG, "dev_buf must be device memory, not host memory");
+  }
   lbm_lattice* h = new (std::nothrow) lbm_lattice();
   if (!h) return fail(LBM_ERR_OUT_OF_MEMORY, "host allocation failed");
   h->p = *p;
   h->d = d;
   h->stream = (hipStream_t)stream;
+  h->device = device;
   h->q = p->lattice;
   h->prec = p->precision;
   h->energy = p->energy;
@@ -744,17 +864,30 @@ extern "C" lbm_status lbm_step(lbm_lattice* h, int64_t nsteps) {
 extern "C" lbm_status lbm_fields(lbm_lattice* h, double* rho, double* ux, double* uy, double* uz, double* T) {
   if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
   if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_fields (use lbm_enthalpy_fields) is not available for enthalpy lattices");
+  const void* ptrs[5] = {rho, ux, uy, uz, T};
+  const size_t fb = (size_t)h->nodes * sizeof(double);
+  const size_t sizes[5] = {fb, fb, fb, fb, fb};
+  const char* names[5] = {"rho", "ux", "uy", "uz", "T"};
+  Staging io(h->stream);
+  lbm_status st = io.resolve(h->device, ptrs, sizes, names, 5);
+  if (st != LBM_OK) return st;
+  double* d[5];
+  for (int i = 0; i < 5; ++i) d[i] = static_cast<double*>(io.dev[i]);
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
     const S st_ = make_store<S>(h);
     if (h->parity)
-      hipLaunchKernelGGL((k_fields<Lat, S, C, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, rho, ux, uy, uz, T);
+      hipLaunchKernelGGL((k_fields<Lat, S, C, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, d[0], d[1], d[2], d[3], d[4]);
     else
-      hipLaunchKernelGGL((k_fields<Lat, S, C, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, rho, ux, uy, uz, T);
+      hipLaunchKernelGGL((k_fields<Lat, S, C, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, d[0], d[1], d[2], d[3], d[4]);
   });
-  return launch_check("fields");
+  st = launch_check("fields");
+  if (st != LBM_OK) return st;
+  st = io.to_host();
+  if (st != LBM_OK) return st;
+  return io.finish();
 }
 
 extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {
@@ -833,79 +966,120 @@ extern "C" lbm_status lbm_totals(lbm_lattice* h, double* mass, double* heat) {
 
 extern "C" lbm_status lbm_get_state(lbm_lattice* h, double* f, double* g) {
   if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
+  if (h->energy && f) return fail(LBM_ERR_INVALID_ARG, "an enthalpy lattice has no flow populations (f must be NULL)");
+  const void* ptrs[2] = {f, g};
+  const size_t sizes[2] = {(size_t)h->q * h->nodes * sizeof(double), (size_t)7 * h->nodes * sizeof(double)};
+  const char* names[2] = {"f", "g"};
+  Staging io(h->stream);
+  lbm_status st = io.resolve(h->device, ptrs, sizes, names, 2);
+  if (st != LBM_OK) return st;
+  double* df = static_cast<double*>(io.dev[0]);
+  double* dg = static_cast<double*>(io.dev[1]);
   if (h->energy) {
-    if (f) return fail(LBM_ERR_INVALID_ARG, "an enthalpy lattice has no flow populations (f must be NULL)");
     if (!g) return LBM_OK;
     if (h->prec == LBM_FP64) {
       using S = Store<double, double, double>;
-      if (h->parity) hipLaunchKernelGGL((k_get_g<S, double, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, make_store<S>(h), g);
-      else hipLaunchKernelGGL((k_get_g<S, double, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, make_store<S>(h), g);
+      if (h->parity) hipLaunchKernelGGL((k_get_g<S, double, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, make_store<S>(h), dg);
+      else hipLaunchKernelGGL((k_get_g<S, double, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, make_store<S>(h), dg);
     } else {
       using S = Store<float, float, float>;
-      if (h->parity) hipLaunchKernelGGL((k_get_g<S, float, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, make_store<S>(h), g);
-      else hipLaunchKernelGGL((k_get_g<S, float, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, make_store<S>(h), g);
+      if (h->parity) hipLaunchKernelGGL((k_get_g<S, float, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, make_store<S>(h), dg);
+      else hipLaunchKernelGGL((k_get_g<S, float, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, make_store<S>(h), dg);
     }
-    return launch_check("get_state");
+  } else {
+    with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
+      using Lat = decltype(lat);
+      using S = decltype(s_t);
+      using C = decltype(c_t);
+      const S st_ = make_store<S>(h);
+      if (h->parity)
+        hipLaunchKernelGGL((k_get_state<Lat, S, C, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, df, dg);
+      else
+        hipLaunchKernelGGL((k_get_state<Lat, S, C, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, df, dg);
+    });
   }
-  with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
-    using Lat = decltype(lat);
-    using S = decltype(s_t);
-    using C = decltype(c_t);
-    const S st_ = make_store<S>(h);
-    if (h->parity)
-      hipLaunchKernelGGL((k_get_state<Lat, S, C, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, f, g);
-    else
-      hipLaunchKernelGGL((k_get_state<Lat, S, C, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, f, g);
-  });
-  return launch_check("get_state");
+  st = launch_check("get_state");
+  if (st != LBM_OK) return st;
+  st = io.to_host();
+  if (st != LBM_OK) return st;
+  return io.finish();
 }
 
 extern "C" lbm_status lbm_set_state(lbm_lattice* h, const double* f, const double* g) {
-  if (h && h->energy) {
+  if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
+  if (h->energy) {
     if (f || !g) return fail(LBM_ERR_INVALID_ARG, "an enthalpy lattice takes g only (f must be NULL)");
+  } else if (!f || !g) {
+    return fail(LBM_ERR_INVALID_ARG, "lbm_set_state needs both f and g");
+  }
+  if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice is in a batch: remove it first");
+  const void* ptrs[2] = {f, g};
+  const size_t sizes[2] = {(size_t)h->q * h->nodes * sizeof(double), (size_t)7 * h->nodes * sizeof(double)};
+  const char* names[2] = {"f", "g"};
+  Staging io(h->stream);
+  lbm_status st = io.resolve(h->device, ptrs, sizes, names, 2);
+  if (st != LBM_OK) return st;
+  st = io.from_host();
+  if (st != LBM_OK) return st;
+  const double* df = static_cast<const double*>(io.dev[0]);
+  const double* dg = static_cast<const double*>(io.dev[1]);
+  if (h->energy) {
     if (h->prec == LBM_FP64) {
       using S = Store<double, double, double>;
-      hipLaunchKernelGGL((k_set_g<S, double>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, make_store<S>(h), g);
+      hipLaunchKernelGGL((k_set_g<S, double>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, make_store<S>(h), dg);
     } else {
       using S = Store<float, float, float>;
-      hipLaunchKernelGGL((k_set_g<S, float>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, make_store<S>(h), g);
+      hipLaunchKernelGGL((k_set_g<S, float>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, make_store<S>(h), dg);
     }
-    lbm_status ls = launch_check("set_state");
-    if (ls != LBM_OK) return ls;
+    st = launch_check("set_state");
+    if (st != LBM_OK) return st;
     h->parity = 0;
-    return LBM_OK;
+    return io.finish();
   }
-  if (!h || !f || !g) return fail(LBM_ERR_INVALID_ARG, "lbm_set_state needs both f and g");
-  if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice is in a batch: remove it first");
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
     hipLaunchKernelGGL((k_set_state<Lat, S, C>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp,
-                       make_store<S>(h), f, g);
+                       make_store<S>(h), df, dg);
   });
-  lbm_status ls = launch_check("set_state");
-  if (ls != LBM_OK) return ls;
+  st = launch_check("set_state");
+  if (st != LBM_OK) return st;
   h->parity = 0;
   h->snapshot_valid = false;
-  return set_clock(h);
+  st = set_clock(h);
+  if (st != LBM_OK) return st;
+  return io.finish();
 }
 
 extern "C" lbm_status lbm_enthalpy_fields(lbm_lattice* h, double* T, double* En, double* fl) {
   if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
   if (!h->energy) return fail(LBM_ERR_UNSUPPORTED, "not an enthalpy lattice (use lbm_fields)");
+  const void* ptrs[3] = {T, En, fl};
+  const size_t fb = (size_t)h->nodes * sizeof(double);
+  const size_t sizes[3] = {fb, fb, fb};
+  const char* names[3] = {"T", "En", "fl"};
+  Staging io(h->stream);
+  lbm_status st = io.resolve(h->device, ptrs, sizes, names, 3);
+  if (st != LBM_OK) return st;
+  double* d[3];
+  for (int i = 0; i < 3; ++i) d[i] = static_cast<double*>(io.dev[i]);
   if (h->prec == LBM_FP64) {
     using S = Store<double, double, double>;
     const EnthalpyConsts<double> ec = enthalpy_consts<double>(&h->p);
-    if (h->parity) hipLaunchKernelGGL((k_fields_enthalpy<S, double, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, ec, make_store<S>(h), T, En, fl);
-    else hipLaunchKernelGGL((k_fields_enthalpy<S, double, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, ec, make_store<S>(h), T, En, fl);
+    if (h->parity) hipLaunchKernelGGL((k_fields_enthalpy<S, double, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, ec, make_store<S>(h), d[0], d[1], d[2]);
+    else hipLaunchKernelGGL((k_fields_enthalpy<S, double, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kd, ec, make_store<S>(h), d[0], d[1], d[2]);
   } else {
     using S = Store<float, float, float>;
     const EnthalpyConsts<float> ec = enthalpy_consts<float>(&h->p);
-    if (h->parity) hipLaunchKernelGGL((k_fields_enthalpy<S, float, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, ec, make_store<S>(h), T, En, fl);
-    else hipLaunchKernelGGL((k_fields_enthalpy<S, float, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, ec, make_store<S>(h), T, En, fl);
+    if (h->parity) hipLaunchKernelGGL((k_fields_enthalpy<S, float, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, ec, make_store<S>(h), d[0], d[1], d[2]);
+    else hipLaunchKernelGGL((k_fields_enthalpy<S, float, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, h->kf, ec, make_store<S>(h), d[0], d[1], d[2]);
   }
-  return launch_check("enthalpy fields");
+  st = launch_check("enthalpy fields");
+  if (st != LBM_OK) return st;
+  st = io.to_host();
+  if (st != LBM_OK) return st;
+  return io.finish();
 }
 
 extern "C" lbm_status lbm_transfer_state(lbm_lattice* dst, lbm_lattice* src) {

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch  # loads the HIP runtime that liblbm.so then shares
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -192,8 +193,13 @@ def required_bytes(params: Params) -> int:
 
 
 def _ptr(t) -> ctypes.c_void_p | None:
+    """Address of an FP64 buffer: a contiguous CUDA tensor (device memory) or
+    a C-contiguous numpy array (host memory, which the library stages)."""
     if t is None:
         return None
+    if isinstance(t, np.ndarray):
+        assert t.dtype == np.float64 and t.flags["C_CONTIGUOUS"]
+        return ctypes.c_void_p(t.ctypes.data)
     assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
     return ctypes.c_void_p(t.data_ptr())
 
@@ -264,11 +270,17 @@ class Lattice:
         return {k: getattr(d, k) for k, _ in Derived._fields_}
 
     # -- outputs
-    def fields(self) -> dict:
-        out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device)
-               for k in ("rho", "ux", "uy", "uz", "T")}
-        _check(_lib.lbm_fields(self._h, *(_ptr(out[k]) for k in ("rho", "ux", "uy", "uz", "T"))))
-        self._settle()
+    def fields(self, host: bool = False) -> dict:
+        """rho, ux, uy, uz, T: FP64 device tensors, or numpy arrays written by
+        the library through host pointers (host=True)."""
+        keys = ("rho", "ux", "uy", "uz", "T")
+        if host:
+            out = {k: np.empty(self.shape, dtype=np.float64) for k in keys}
+        else:
+            out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device) for k in keys}
+        _check(_lib.lbm_fields(self._h, *(_ptr(out[k]) for k in keys)))
+        if not host:
+            self._settle()
         return out
 
     def nusselt(self):
@@ -288,20 +300,33 @@ class Lattice:
         _check(_lib.lbm_totals(self._h, ctypes.byref(m), ctypes.byref(q)))
         return float(m.value), float(q.value)
 
-    def get_state(self):
-        """(f, g) pre-collision populations, FP64 device tensors; f is None for
-        an enthalpy lattice."""
-        f = None if self.enthalpy else torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
-        g = torch.empty((7,) + self.shape, dtype=torch.float64, device=self.device)
+    def get_state(self, host: bool = False):
+        """(f, g) pre-collision populations, FP64 device tensors (numpy arrays
+        through host pointers with host=True); f is None for an enthalpy
+        lattice."""
+        if host:
+            f = None if self.enthalpy else np.empty((self.q,) + self.shape, dtype=np.float64)
+            g = np.empty((7,) + self.shape, dtype=np.float64)
+        else:
+            f = None if self.enthalpy else torch.empty((self.q,) + self.shape, dtype=torch.float64,
+                                                       device=self.device)
+            g = torch.empty((7,) + self.shape, dtype=torch.float64, device=self.device)
         _check(_lib.lbm_get_state(self._h, _ptr(f), _ptr(g)))
-        self._settle()
+        if not host:
+            self._settle()
         return f, g
 
-    def enthalpy_fields(self) -> dict:
-        """T, En and f_l (Eqs. B7-B9) of an enthalpy lattice."""
-        out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device) for k in ("T", "En", "fl")}
-        _check(_lib.lbm_enthalpy_fields(self._h, _ptr(out["T"]), _ptr(out["En"]), _ptr(out["fl"])))
-        self._settle()
+    def enthalpy_fields(self, host: bool = False) -> dict:
+        """T, En and f_l (Eqs. B7-B9) of an enthalpy lattice (numpy arrays
+        through host pointers with host=True)."""
+        keys = ("T", "En", "fl")
+        if host:
+            out = {k: np.empty(self.shape, dtype=np.float64) for k in keys}
+        else:
+            out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device) for k in keys}
+        _check(_lib.lbm_enthalpy_fields(self._h, *(_ptr(out[k]) for k in keys)))
+        if not host:
+            self._settle()
         return out
 
     def transfer_from(self, other: "Lattice"):
@@ -310,12 +335,19 @@ class Lattice:
         _check(_lib.lbm_transfer_state(self._h, other._h))
 
     def set_state(self, f, g):
-        """Replaces the state (f must be None for an enthalpy lattice)."""
-        g = torch.as_tensor(g, dtype=torch.float64).to(self.device).contiguous()
-        assert tuple(g.shape) == (7,) + self.shape
+        """Replaces the state (f must be None for an enthalpy lattice).  numpy
+        arrays are passed as host memory (the library stages them); anything
+        else is moved to the device first."""
+        def arr(a, lead):
+            if isinstance(a, np.ndarray):
+                a = np.ascontiguousarray(a, dtype=np.float64)
+            else:
+                a = torch.as_tensor(a, dtype=torch.float64).to(self.device).contiguous()
+            assert tuple(a.shape) == (lead,) + self.shape
+            return a
+        g = arr(g, 7)
         if f is not None:
-            f = torch.as_tensor(f, dtype=torch.float64).to(self.device).contiguous()
-            assert tuple(f.shape) == (self.q,) + self.shape
+            f = arr(f, self.q)
         _check(_lib.lbm_set_state(self._h, _ptr(f), _ptr(g)))
         # keep the inputs alive until the copy kernel has run
         self.stream.synchronize()
