@@ -206,6 +206,23 @@ lbm_status lbm_derived_params(const lbm_lattice* h, lbm_derived* d);
  * field.  Asynchronous for device buffers; synchronizes when one is host memory. */
 lbm_status lbm_fields(lbm_lattice* h, double* rho, double* ux, double* uy, double* uz, double* T);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation): the
+ * output of lbm_fields, bit for bit, with no allocation.  Same arguments,
+ * layout and NULL rule as lbm_fields.  Device buffers are written directly
+ * (asynchronous, as lbm_fields).  Host buffers (pinned or pageable) pass
+ * through a staging array the library holds in its own device code object, 16
+ * MiB per device, kept until the process ends: the lattice is processed in
+ * passes of at most 16 MiB / (8 B x number of host outputs) nodes, each pass's
+ * kernel followed by its copies to the host, and the call synchronizes the
+ * lattice's stream before it returns.  Any lattice size is accepted: a larger
+ * lattice takes more passes.  Calls no hipMalloc, hipFree or other allocating
+ * routine.  Every call on a device shares that device's one array: calls that
+ * overlap on one device (other threads, other streams) race and must be
+ * serialized by the caller.  Errors as lbm_fields (LBM_ERR_INVALID_ARG for
+ * memory of another device, LBM_ERR_UNSUPPORTED for an enthalpy lattice). */
+lbm_status lbm_fields_noalloc(lbm_lattice* h, double* rho, double* ux, double* uy, double* uz, double* T);
+
 /* Face Nusselt numbers at the current time, FP64, into host nu[6]: for every
  * isothermal face, the mean over the face's nodes of the heat that entered the
  * fluid through it during the last streaming (2 g_k - 2 omega_k sigma T_w for

@@ -773,23 +773,25 @@ __global__ void __launch_bounds__(kMaxBlock) k_init(const KParams<C> kp, const I
 }
 
 // ------------------------------------------------------------------ fields
+// Nodes [n0, n0 + count) of the lattice; output element n - n0 holds node n.
 template <class Lat, class S, class C, bool ODD>
-__global__ void __launch_bounds__(kMaxBlock) k_fields(const KParams<C> kp, const S state,
+__global__ void __launch_bounds__(kMaxBlock) k_fields(const KParams<C> kp, const S state, int n0, int count,
                                                       double* rho, double* ux, double* uy, double* uz,
                                                       double* T) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= kp.n) return;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= count) return;
+  const int n = n0 + m;
   int x, y, z;
   node_coords(kp, n, x, y, z);
   const Nbr nb = make_nbr(kp, x, y, z);
   C h[Lat::Q], p[7];
   gather<Lat, ODD, true, S, C>(kp, state, n, nb, h, p);
   const Macro<C> M = macro<Lat, C>(kp, h, p);
-  if (rho) rho[n] = 1.0 + (double)M.drho;
-  if (ux) ux[n] = (double)M.ux;
-  if (uy) uy[n] = (double)M.uy;
-  if (uz) uz[n] = (double)M.uz;
-  if (T) T[n] = (double)M.T;
+  if (rho) rho[m] = 1.0 + (double)M.drho;
+  if (ux) ux[m] = (double)M.ux;
+  if (uy) uy[m] = (double)M.uy;
+  if (uz) uz[m] = (double)M.uz;
+  if (T) T[m] = (double)M.T;
 }
 
 // Per-block FP64 sums of (rho - rho0) and sigma (T - T_ref) of the current state.

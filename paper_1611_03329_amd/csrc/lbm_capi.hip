@@ -17,6 +17,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 using namespace lbm;
@@ -879,15 +880,107 @@ extern "C" lbm_status lbm_fields(lbm_lattice* h, double* rho, double* ux, double
     using C = decltype(c_t);
     const S st_ = make_store<S>(h);
     if (h->parity)
-      hipLaunchKernelGGL((k_fields<Lat, S, C, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, d[0], d[1], d[2], d[3], d[4]);
+      hipLaunchKernelGGL((k_fields<Lat, S, C, true>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, 0,
+                         h->nodes, d[0], d[1], d[2], d[3], d[4]);
     else
-      hipLaunchKernelGGL((k_fields<Lat, S, C, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, d[0], d[1], d[2], d[3], d[4]);
+      hipLaunchKernelGGL((k_fields<Lat, S, C, false>), dim3(h->nblocks), dim3(h->block), 0, h->stream, kp, st_, 0,
+                         h->nodes, d[0], d[1], d[2], d[3], d[4]);
   });
   st = launch_check("fields");
   if (st != LBM_OK) return st;
   st = io.to_host();
   if (st != LBM_OK) return st;
   return io.finish();
+}
+
+// ------------------------------------------------------------------ allocation-free fields
+// Staging memory of lbm_fields_noalloc: an array of the library's own device
+// code object, one copy per device, held until the process ends.  Host code
+// never uses its name as an address: the device address is looked up once per
+// device (hipGetSymbolAddress, with that device current) and kept in
+// g_scratch; kernels and copies get that address.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices];
+
+static lbm_status scratch_of(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(LBM_ERR_UNSUPPORTED, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) HIP_TRY(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+      return fail(LBM_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                  hipGetErrorString(e));
+    g_scratch[device] = ptr;
+  }
+  *out = g_scratch[device];
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_fields_noalloc(lbm_lattice* h, double* rho, double* ux, double* uy, double* uz,
+                                         double* T) {
+  if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
+  if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_fields_noalloc is not available for enthalpy lattices");
+  double* user[5] = {rho, ux, uy, uz, T};
+  const char* names[5] = {"rho", "ux", "uy", "uz", "T"};
+  bool host[5] = {};
+  int nhost = 0;
+  for (int i = 0; i < 5; ++i) {
+    if (!user[i]) continue;
+    MemKind k;
+    lbm_status st = classify(user[i], h->device, names[i], &k);
+    if (st != LBM_OK) return st;
+    host[i] = k == MemKind::Host;
+    nhost += host[i] ? 1 : 0;
+  }
+  void* sp = nullptr;
+  if (nhost > 0) {
+    lbm_status st = scratch_of(h->device, &sp);
+    if (st != LBM_OK) return st;
+  }
+  // nodes per pass: every host field's slice of the pass fits the array
+  const int chunk = nhost > 0 ? (int)std::min<size_t>((size_t)h->nodes, kScratchBytes / (sizeof(double) * nhost))
+                              : h->nodes;
+  for (int n0 = 0; n0 < h->nodes; n0 += chunk) {
+    const int cnt = std::min(chunk, h->nodes - n0);
+    double* d[5];
+    int slot = 0;
+    for (int i = 0; i < 5; ++i) {
+      if (!user[i]) d[i] = nullptr;
+      else if (host[i]) d[i] = static_cast<double*>(sp) + (size_t)(slot++) * chunk;
+      else d[i] = user[i] + n0;
+    }
+    const dim3 grid((unsigned)((cnt + h->block - 1) / h->block));
+    with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
+      using Lat = decltype(lat);
+      using S = decltype(s_t);
+      using C = decltype(c_t);
+      const S st_ = make_store<S>(h);
+      if (h->parity)
+        hipLaunchKernelGGL((k_fields<Lat, S, C, true>), grid, dim3(h->block), 0, h->stream, kp, st_, n0, cnt, d[0],
+                           d[1], d[2], d[3], d[4]);
+      else
+        hipLaunchKernelGGL((k_fields<Lat, S, C, false>), grid, dim3(h->block), 0, h->stream, kp, st_, n0, cnt, d[0],
+                           d[1], d[2], d[3], d[4]);
+    });
+    lbm_status st = launch_check("fields_noalloc");
+    if (st != LBM_OK) return st;
+    // stream order: the next pass's kernel overwrites the array only after
+    // these copies have read it
+    for (int i = 0; i < 5; ++i)
+      if (host[i])
+        HIP_TRY(hipMemcpyAsync(user[i] + n0, d[i], (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  }
+  if (nhost > 0) HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
 }
 
 extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {

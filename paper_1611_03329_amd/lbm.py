@@ -106,6 +106,7 @@ _lib.lbm_step.argtypes = [_V, ctypes.c_int64]
 _lib.lbm_time.argtypes = [_V, _I64]
 _lib.lbm_derived_params.argtypes = [_V, ctypes.POINTER(Derived)]
 _lib.lbm_fields.argtypes = [_V, _V, _V, _V, _V, _V]
+_lib.lbm_fields_noalloc.argtypes = [_V, _V, _V, _V, _V, _V]
 _lib.lbm_enthalpy_fields.argtypes = [_V, _V, _V, _V]
 _lib.lbm_nusselt.argtypes = [_V, _D]
 _lib.lbm_residual.argtypes = [_V, _D, _I64]
@@ -130,7 +131,7 @@ _lib.lbm_batch_autotune.argtypes = [_V, ctypes.POINTER(Launch)]
 _lib.lbm_batch_set_graph.argtypes = [_V, ctypes.c_int32]
 _lib.lbm_batch_set_span.argtypes = [_V, ctypes.c_int32]
 for _name in ("lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_step",
-              "lbm_time", "lbm_derived_params", "lbm_fields", "lbm_nusselt", "lbm_residual",
+              "lbm_time", "lbm_derived_params", "lbm_fields", "lbm_fields_noalloc", "lbm_nusselt", "lbm_residual",
               "lbm_totals", "lbm_get_state", "lbm_set_state", "lbm_transfer_state", "lbm_enthalpy_fields", "lbm_batch_create", "lbm_batch_destroy",
               "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size", "lbm_batch_member", "lbm_batch_step",
               "lbm_batch_residuals", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_set_graph",
