@@ -58,7 +58,7 @@ PEAK_VALU_WAVE_INSTR_PER_S = 256 * 2.4e9
 # everything the step kernel is compiled from, build flags included
 KERNEL_SOURCES = ("paper_1611_03329_amd/csrc/kernels.hpp", "paper_1611_03329_amd/csrc/model.hpp",
                   "paper_1611_03329_amd/csrc/lattice.hpp", "paper_1611_03329_amd/csrc/batch.hpp",
-                  "paper_1611_03329_amd/build.py")
+                  "paper_1611_03329_amd/csrc/lbm_capi.hip", "paper_1611_03329_amd/build.py")
 
 
 def kernel_hash() -> str:
@@ -147,13 +147,73 @@ def tune_launch(workloads, precision: str, interval: int):
     return shape
 
 
+def run_solves(reqs, runs, args, budget=None, progress=_say) -> dict:
+    """Serves the requests once per entry of `runs` ((name, precision,
+    policy, node cap) tuples) and solves them one after another in plain FP32
+    (name "sequential_fp32"), all to residual 1e-6 with the launch shape the
+    autotuner picks for the first --tune-count workloads.  Returns name ->
+    (results, summary) and the launch shape."""
+    from paper_1611_03329_amd.serve import Server, solve_sequential, summarize
+    shape = tune_launch([q.workload for q in reqs[:args.tune_count]], "fp32", 100)
+    progress(f"launch shape (threads, blocks/CU, group bytes, XCD ranges) = {shape}")
+    out = {}
+    for name, prec, policy, max_nodes in runs:
+        with Server(prec, check_interval=100, tol=1e-6, max_steps=args.max_steps, hbm_budget=budget,
+                    launch=shape, policy=policy, max_nodes=max_nodes) as srv:
+            res = srv.run(reqs, progress=progress)
+            stats = dict(srv.stats)
+        out[name] = (res, {**summarize(res), "promoted": stats["promoted"],
+                           "peak_members": stats["peak_members"], "peak_bytes": stats["peak_bytes"]})
+        progress(f"served {name}: {out[name][1]}")
+    seq = solve_sequential(reqs, "fp32", check_interval=100, tol=1e-6, max_steps=args.max_steps, progress=progress)
+    out["sequential_fp32"] = (seq, summarize(seq))
+    progress(f"sequential fp32: {out['sequential_fp32'][1]}")
+    return out, shape
+
+
+def nu_rel_diff(res, ref) -> dict:
+    """Largest and median relative difference of the hot-wall Nu between two
+    runs of the same requests, over the requests both converged."""
+    d = sorted(abs(a.nu[0] - b.nu[0]) / abs(b.nu[0]) for a, b in zip(res, ref)
+               if a.converged and b.converged and a.nu and b.nu)
+    return {"max": d[-1] if d else None, "median": d[len(d) // 2] if d else None, "count": len(d)}
+
+
+def batched_object(args) -> dict:
+    """The batched-solve half of the headline metric on the default line: the
+    64 cavities of uneven sizes and parameters, all submitted at t = 0, served
+    with continuous batching in FP32 (smallest first under the resident-node
+    cap) against the same 64 solved one after another in plain FP32."""
+    import lbm_inputs
+    from paper_1611_03329_amd.serve import Request
+    reqs = [Request(i, 0.0, w) for i, w in enumerate(lbm_inputs.config_batch(args.count))]
+    nodes = sum(q.workload["nx"] * q.workload["ny"] * q.workload["nz"] for q in reqs)
+    cap = int(args.smallest_first_mnodes * 1e6)
+    _say(f"batched: {len(reqs)} cavities, {nodes} nodes")
+    runs, shape = run_solves(reqs, [("served_fp32_smallest_first", "fp32", "smallest", cap)], args,
+                             progress=lambda m: None)
+    served, seq = runs["served_fp32_smallest_first"][1], runs["sequential_fp32"][1]
+    _say(f"batched: served {served['solves_per_s']:.4f} solves/s p50 {served['p50_s']:.1f} s; "
+         f"sequential {seq['solves_per_s']:.4f} solves/s p50 {seq['p50_s']:.1f} s")
+    return {
+        "workload": f"{len(reqs)} porous cavities, edge from {{32,48,64,96,128}}, phi U[0.3,0.9], Da logU[1e-5,1e-1], "
+                    "Ra logU[1e3,1e6], Pr 1, FP32, seed 4, all submitted at t=0, each to residual 1e-6",
+        "requests": len(reqs), "nodes": nodes, "max_steps": args.max_steps, "launch": list(shape),
+        "served_fp32_smallest_first": {**served, "max_resident_nodes": cap},
+        "sequential_fp32": seq,
+        "speedup_solves_per_s": round(served["solves_per_s"] / seq["solves_per_s"], 4),
+        "nu_hot_rel_diff_vs_sequential": nu_rel_diff(runs["served_fp32_smallest_first"][0],
+                                                     runs["sequential_fp32"][0]),
+    }
+
+
 def bench_solves(args, kind: str) -> int:
     """Solves to residual 1e-6, served with continuous batching (FP32, and FP16
     storage with the FP32 finish) against one-after-another plain FP32 solves."""
     import torch
 
     import lbm_inputs
-    from paper_1611_03329_amd.serve import Request, Server, as_requests, solve_sequential, summarize
+    from paper_1611_03329_amd.serve import Request, as_requests
 
     torch.cuda.set_device(0)
     if kind == "batched":
@@ -170,27 +230,10 @@ def bench_solves(args, kind: str) -> int:
         metric = "served-solve throughput and p50/p99 time-to-converge (residual 1e-6)"
     nodes = sum(q.workload["nx"] * q.workload["ny"] * q.workload["nz"] for q in reqs)
     _say(f"{kind}: {len(reqs)} requests, {nodes} nodes in all; tuning the launch shape")
-    shape = tune_launch([q.workload for q in reqs[:args.tune_count]], "fp32", 100)
-    _say(f"launch shape (threads, blocks/CU, group bytes) = {shape}")
-    runs = {}
     cap = int(args.smallest_first_mnodes * 1e6)
-    for name, prec, policy, max_nodes in (("fp32", "fp32", "fcfs", None), ("fp16", "fp16", "fcfs", None),
-                                          ("fp32_smallest_first", "fp32", "smallest", cap)):
-        with Server(prec, check_interval=100, tol=1e-6, max_steps=args.max_steps, hbm_budget=budget,
-                    launch=shape, policy=policy, max_nodes=max_nodes) as srv:
-            res = srv.run(reqs, progress=_say)
-            stats = dict(srv.stats)
-        runs[name] = (res, {**summarize(res), "promoted": stats["promoted"],
-                            "peak_members": stats["peak_members"], "peak_bytes": stats["peak_bytes"]})
-        _say(f"served {name}: {runs[name][1]}")
-    seq = solve_sequential(reqs, "fp32", check_interval=100, tol=1e-6, max_steps=args.max_steps, progress=_say)
-    q_sum = summarize(seq)
-    _say(f"sequential fp32: {q_sum}")
-
-    def nu_diff(res):
-        d = sorted(abs(a.nu[0] - b.nu[0]) / abs(b.nu[0]) for a, b in zip(res, seq) if a.nu and b.nu)
-        return {"max": d[-1] if d else None, "median": d[len(d) // 2] if d else None}
-
+    runs, shape = run_solves(reqs, (("fp32", "fp32", "fcfs", None), ("fp16", "fp16", "fcfs", None),
+                                    ("fp32_smallest_first", "fp32", "smallest", cap)), args, budget=budget)
+    seq_res, q_sum = runs.pop("sequential_fp32")
     main_sum = runs["fp32"][1]
     line = {
         "metric": metric,
@@ -209,7 +252,7 @@ def bench_solves(args, kind: str) -> int:
         "served_fp32_smallest_first": {**runs["fp32_smallest_first"][1], "max_resident_nodes": cap},
         "sequential_fp32": q_sum,
         "speedup_solves_per_s": {p: round(runs[p][1]["solves_per_s"] / q_sum["solves_per_s"], 3) for p in runs},
-        "nu_hot_rel_diff_vs_sequential": {p: nu_diff(runs[p][0]) for p in runs},
+        "nu_hot_rel_diff_vs_sequential": {p: nu_rel_diff(runs[p][0], seq_res) for p in runs},
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -462,6 +505,9 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-steps-one-thread", type=int, default=1,
                     help="oracle steps on the 256^3 sample on one thread (0 skips them)")
     ap.add_argument("--oracle-only", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--batched", action=argparse.BooleanOptionalAction, default=True,
+                    help="cavity256: also run the batched-solve benchmark (64 cavities to residual 1e-6, served "
+                         "FP32 against one after another) and report it in the same line")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain device-to-device copy timed as the attainable-bandwidth "
                          "reference (0 skips it)")
@@ -530,8 +576,13 @@ def main(argv=None) -> int:
     r, at = lat.residual()
     nu = lat.nusselt()
     lat.close()
-    print(f"[bench] {ms_per_step:.4f} ms/step, {mlups:.1f} MLUPS, residual {r:.3e} at {at}, "
-          f"Nu_hot {nu[0]:.5f}", file=sys.stderr, flush=True)
+    # compare steps (residual checks) that ran inside the timed region: the
+    # steps starting at times t = warmup .. warmup + steps - 1 with t % K == 0
+    K = args.check_interval
+    t0, t1 = args.warmup, args.warmup + args.steps - 1
+    checks = 0 if K <= 0 else max(0, t1 // K - max(t0 - 1, K - 1) // K)
+    print(f"[bench] {ms_per_step:.4f} ms/step, {mlups:.1f} MLUPS, residual {r:.3e} at {at} "
+          f"({checks} checks timed), Nu_hot {nu[0]:.5f}", file=sys.stderr, flush=True)
 
     fp16 = args.precision == "fp16"
     bytes_per_node = 2 * (18 * 2 + 8 * 4) if fp16 else 2 * (19 + 7) * 4
@@ -547,6 +598,8 @@ def main(argv=None) -> int:
         roofline["valu_issue"] = None if valu is None else {
             "wave_instructions_per_step": valu,
             "per_cu_per_clock": round(valu / (ms_per_step / 1e3) / PEAK_VALU_WAVE_INSTR_PER_S, 4)}
+
+    batched = batched_object(args) if args.batched else None
 
     cpu = None
     if args.cpu_steps > 0:
@@ -574,12 +627,16 @@ def main(argv=None) -> int:
         "config": {
             "workload": "porous cavity 256^3, D3Q19 MRT flow + D3Q7 MRT temperature, "
                         + ("FP16 flow storage (stochastic rounding), FP32 arithmetic, " if fp16 else "FP32, ")
-                        + "phi 0.4, Da 1e-4, Ra 1e6, Pr 1, seed 2, residual check every "
-                        f"{args.check_interval} steps",
+                        + "phi 0.4, Da 1e-4, Ra 1e6, Pr 1, seed 2"
+                        + (f", residual check every {K} steps ({checks} in the timed region)" if checks else
+                           ", no residual check in the timed region"),
             "nodes": nodes,
+            "check_interval": K,
+            "checks_in_timed_region": checks,
             "parallelism": "single GPU",
         },
         "roofline": roofline,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

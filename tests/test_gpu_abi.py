@@ -48,6 +48,8 @@ def test_host_buffers_equal_device_buffers(prec):
         f1 = fh * (1.0 + 1e-3 * rng.standard_normal(fh.shape))
         g1 = gh + 1e-3 * rng.standard_normal(gh.shape)
         with Lattice(wl, prec) as other:
+            # the same time counter: FP16 storage draws its rounding bits from it
+            other.step(lat.time)
             lat.set_state(f1, g1)                                    # numpy: host memory
             other.set_state(torch.from_numpy(f1).cuda(), torch.from_numpy(g1).cuda())
             a_f, a_g = lat.get_state(host=True)
