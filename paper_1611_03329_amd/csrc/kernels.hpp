@@ -61,6 +61,21 @@ __device__ __forceinline__ void st(S* base, uint32_t e, C v) {
     *(LBM_GLOBAL S*)(b + e * (uint32_t)sizeof(S)) = static_cast<S>(v);
 }
 
+// The step kernels take FP16 flow populations as they are stored, times
+// kHalfScale, and carry the whole flow state (the rest population too) at that
+// scale through the collision (see model.hpp); no population is scaled on its
+// way in or out.  Other kernels use ld / st, which convert.
+template <class S>
+constexpr int kFlowScale = std::is_same<typename S::MoveF, _Float16>::value ? (int)kHalfScale : 1;
+
+template <class S, class C>
+__device__ __forceinline__ C ld_raw(const S* base, uint32_t e) {
+  const LBM_GLOBAL char* b = (const LBM_GLOBAL char*)base;
+  const S x = *(const LBM_GLOBAL S*)(b + e * (uint32_t)sizeof(S));
+  if constexpr (std::is_same<S, _Float16>::value) return static_cast<C>((float)x);
+  else return static_cast<C>(x);
+}
+
 // Population storage in three regions: the moving flow populations f_1..f_{Q-1}
 // (type Mf), the moving temperature populations g_1..g_6 (type Mg) and the two
 // rest populations f_0, g_0 (type Rs), which never leave their node.  With FP16
@@ -99,6 +114,12 @@ __device__ __forceinline__ uint32_t rslot(int r, uint32_t n) { return tiled<2u>(
 
 template <class S, class C>
 __device__ __forceinline__ C ld_mf(const S& s, uint32_t e) { return ld<typename S::MoveF, C>(s.mf, e); }
+// moving flow population as the step carries it: times kFlowScale<S> (RAW) or true
+template <bool RAW, class S, class C>
+__device__ __forceinline__ C ld_mf_as(const S& s, uint32_t e) {
+  if constexpr (RAW) return ld_raw<typename S::MoveF, C>(s.mf, e);
+  else return ld<typename S::MoveF, C>(s.mf, e);
+}
 template <class S, class C>
 __device__ __forceinline__ C ld_mg(const S& s, uint32_t e) { return ld<typename S::MoveG, C>(s.mg, e); }
 template <class S, class C>
@@ -116,7 +137,7 @@ __device__ __forceinline__ void st_rs(const S& s, uint32_t e, C v) { st<typename
 // each steady node the same error at every step, a bias that the slow
 // diffusive and Darcy modes accumulate over thousands of steps; a zero-mean
 // error averages out instead.  The random bits are a hash of (step, node)
-// followed by a xorshift sequence over the node's populations, so runs are
+// spread over the node's populations by a Weyl sequence (scatter), so runs are
 // reproducible bit for bit.
 template <class S>
 constexpr bool kStochastic = std::is_same<typename S::MoveF, _Float16>::value;
@@ -131,34 +152,28 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   return x;
 }
 
-// Marsaglia's xorshift32 step (full period over nonzero words).
-__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
-  x ^= x << 13;
-  x ^= x >> 17;
-  x ^= x << 5;
-  return x;
-}
-
-// f to FP16 with the random bits r: add a uniform 13-bit integer to the
+// f to FP16 with the random bits r13 (uniform in [0, 2^13)): add them to the
 // magnitude bits of f below FP16's 10-bit fraction, then cut those 13 bits off,
 // which leaves an FP16 number exactly for magnitudes in FP16's normal range.
 // Below it (2^-14, subnormals: stored departures under 1.5e-8) the conversion
 // then rounds to nearest.  Infinities and the quiet NaN the hardware produces
 // (fraction 0x400000) keep their class: the carry of the added bits never
 // reaches their exponent; magnitudes from 65520 up convert to infinity.
-__device__ __forceinline__ _Float16 half_sr(float f, uint32_t r) {
+__device__ __forceinline__ _Float16 half_sr(float f, uint32_t r13) {
   const uint32_t u = __float_as_uint(f);
-  return (_Float16)__uint_as_float((u + (r & 0x1FFFu)) & ~0x1FFFu);
+  return (_Float16)__uint_as_float((u + r13) & ~0x1FFFu);
 }
 
-// Store of a moving flow population; with FP16 storage r drives the rounding.
-template <class S, class C>
-__device__ __forceinline__ void st_mf_r(const S& s, uint32_t e, C v, uint32_t r) {
+// Store of a moving flow population given as the step carries it (RAW: times
+// kFlowScale<S>; else true); with FP16 storage r13 drives the rounding.
+template <bool RAW, class S, class C>
+__device__ __forceinline__ void st_mf_r(const S& s, uint32_t e, C v, uint32_t r13) {
   if constexpr (kStochastic<S>) {
     LBM_GLOBAL char* b = (LBM_GLOBAL char*)s.mf;
-    *(LBM_GLOBAL _Float16*)(b + e * 2u) = half_sr((float)v * kHalfScale, r);
+    const float f = RAW ? (float)v : (float)v * kHalfScale;
+    *(LBM_GLOBAL _Float16*)(b + e * 2u) = half_sr(f, r13);
   } else {
-    (void)r;
+    (void)r13;
     st_mf<S, C>(s, e, v);
   }
 }
@@ -301,12 +316,13 @@ __host__ __device__ constexpr double weight() {
 // anti-bounce-back of the outgoing post-collision one to twice the even part of
 // f^eq(rho0, u) (Eq. 24 / 18) at the node's own velocity; shifted:
 // h_j = -h*_jbar + 2 w_j [(e_j.u)^2 / (2 phi cs^4) - u^2 / (2 phi cs^2)].
-template <class Lat, int J, class C>
+// (h_out and the result SC times the true values.)
+template <class Lat, int J, int SC, class C>
 __device__ __forceinline__ C open_flow_value(C h_out, const Macro<C>& M, C inv_phi) {
   constexpr int ex = Lat::e(0, J), ey = Lat::e(1, J), ez = Lat::e(2, J);
   const C eu = C(ex) * M.ux + C(ey) * M.uy + C(ez) * M.uz;
   const C uu = M.ux * M.ux + M.uy * M.uy + M.uz * M.uz;
-  return -h_out + C(2.0 * weight<Lat, J>()) * (C(4.5) * eu * eu - C(1.5) * uu) * inv_phi;
+  return -h_out + C(2.0 * SC * weight<Lat, J>()) * (C(4.5) * eu * eu - C(1.5) * uu) * inv_phi;
 }
 
 // Outflow face for g: anti-bounce-back to the node's own temperature;
@@ -342,7 +358,7 @@ __device__ __forceinline__ C wall_term_face(const KParams<C>& kp) {
 // crossing it; a link crossing several faces takes the rule of its exit face
 // (exit_face: the first wall face crossed, else the first open face), and an
 // open exit face brings a value that is already final.
-template <class Lat, class C>
+template <class Lat, int SC, class C>
 __device__ __forceinline__ void gather_walls(const KParams<C>& kp, const Nbr& nb, C (&h)[Lat::Q]) {
   if (!kp.moving) return;
   static_for<0, 6>([&](auto F) {
@@ -354,7 +370,7 @@ __device__ __forceinline__ void gather_walls(const KParams<C>& kp, const Nbr& nb
         if constexpr (crosses<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(f)) {
           bool open;
           const int fc = exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, kp.open_flow, open);
-          const C t = wall_term_face<Lat, i, f, C>(kp);
+          const C t = wall_term_face<Lat, i, f, C>(kp) * C(SC);
           h[i] = (on && fc == f && !open) ? h[i] + t : h[i];
         }
       });
@@ -369,10 +385,11 @@ __device__ __forceinline__ void gather_walls(const KParams<C>& kp, const Nbr& nb
 // parity the open-face value or the moving-wall term, at even parity the
 // open-face value (slot ibar of this node is read back only by this node when
 // i leaves through an open face).  Heat: the outflow value, at both parities.
-template <class Lat, bool ODD, class S, class C>
+template <class Lat, bool ODD, bool RAW, class S, class C>
 __device__ __forceinline__ void scatter_faces(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                               const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M,
                                               uint32_t seed) {
+  constexpr int SC = RAW ? kFlowScale<S> : 1;
   static_for<0, 6>([&](auto F) {
     constexpr int f = decltype(F)::value;
     const bool on = !nb.in[f >> 1][f & 1];
@@ -385,10 +402,10 @@ __device__ __forceinline__ void scatter_faces(const KParams<C>& kp, const S& sto
           bool open;
           const int fc = exit_face<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, kp.open_flow, open);
           if (on && fc == f && (ODD || open)) {
-            const C v = open ? open_flow_value<Lat, io, C>(h[i], M, kp.inv_phi)
-                             : h[i] + wall_term_face<Lat, io, f, C>(kp);
+            const C v = open ? open_flow_value<Lat, io, SC, C>(h[i], M, kp.inv_phi)
+                             : h[i] + wall_term_face<Lat, io, f, C>(kp) * C(SC);
             const uint32_t r = mix32(seed + (uint32_t)n * 0x9E3779B9u + (uint32_t)i * 0x85EBCA6Bu);
-            st_mf_r<S, C>(sto, fslot<Lat>(io, (uint32_t)n), v, r);
+            st_mf_r<RAW, S, C>(sto, fslot<Lat>(io, (uint32_t)n), v, r >> 19);
           }
         }
       });
@@ -413,17 +430,19 @@ __device__ __forceinline__ void scatter_faces(const KParams<C>& kp, const S& sto
 // rules of moving walls and open faces (special faces) as corrections, face by
 // face (gather_walls, scatter_faces).  SEP takes the flow links' indices from
 // tile_deltas (separable tiles only).
-template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false>
+// RAW (the step kernels): the flow populations come out times kFlowScale<S>.
+template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false, bool RAW = false>
 __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                        C (&h)[Lat::Q], C (&p)[7]) {
-  h[0] = ld_rs<S, C>(sto, rslot(0, (uint32_t)n));
+  constexpr int SC = RAW ? kFlowScale<S> : 1;
+  h[0] = ld_rs<S, C>(sto, rslot(0, (uint32_t)n)) * C(SC);
   const uint32_t f1 = fslot<Lat>(1, (uint32_t)n);
   int td[3][2];
   if constexpr (ODD && SEP) tile_deltas<Lat>(nb, n, f1, td);
   static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     if constexpr (!ODD) {
-      h[i] = ld_mf<S, C>(sto, fslot<Lat>(i, (uint32_t)n));
+      h[i] = ld_mf_as<RAW, S, C>(sto, fslot<Lat>(i, (uint32_t)n));
     } else if constexpr (SEP) {
       constexpr int io = Lat::opp(i);
       int dl;
@@ -431,17 +450,17 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n
       link_delta<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, td, dl, in);
       const uint32_t e = f1 + (in ? ((uint32_t)(io - 1) << kTileShift) + (uint32_t)dl
                                   : ((uint32_t)(i - 1) << kTileShift));
-      h[i] = ld_mf<S, C>(sto, e);
+      h[i] = ld_mf_as<RAW, S, C>(sto, e);
     } else {
       constexpr int io = Lat::opp(i);
       int off;
       bool in;
       link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), -1>(nb, off, in);
       const uint32_t e = in ? fslot<Lat>(io, (uint32_t)(n + off)) : fslot<Lat>(i, (uint32_t)n);
-      h[i] = ld_mf<S, C>(sto, e);
+      h[i] = ld_mf_as<RAW, S, C>(sto, e);
     }
   });
-  if constexpr (GEN && ODD) gather_walls<Lat, C>(kp, nb, h);
+  if constexpr (GEN && ODD) gather_walls<Lat, SC, C>(kp, nb, h);
   p[0] = ld_rs<S, C>(sto, rslot(1, (uint32_t)n));
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
@@ -465,43 +484,39 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n
 // ------------------------------------------------------------------ scatter
 // Post-collision shifted populations of node n, written for the next parity.
 // M holds the node's macroscopic state (used by the open-face rules).
-template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false>
+// RAW (the step kernels): h comes in times kFlowScale<S>.
+template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false, bool RAW = false>
 __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                         const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M, uint32_t seed) {
-  st_rs<S, C>(sto, rslot(0, (uint32_t)n), h[0]);
-  // random bits for the stochastic FP16 rounding: one xorshift word serves two
-  // populations (bits 0-12 and 16-28)
-  uint32_t rnd = kStochastic<S> ? (mix32(seed + (uint32_t)n) | 1u) : 0u;
+  constexpr int SC = RAW ? kFlowScale<S> : 1;
+  st_rs<S, C>(sto, rslot(0, (uint32_t)n), h[0] * C(1.0 / SC));
+  // random bits for the stochastic FP16 rounding: one hashed word per node and
+  // step, and for population i the top 13 bits of that word plus i times the
+  // golden-ratio constant (a Weyl sequence): each population's bits are
+  // uniform, and the node's populations take evenly spread rotations of them
+  const uint32_t rnd = kStochastic<S> ? mix32(seed + (uint32_t)n) : 0u;
   const uint32_t f1 = fslot<Lat>(1, (uint32_t)n);
   int td[3][2];
   if constexpr (ODD && SEP) tile_deltas<Lat>(nb, n, f1, td);
   static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int io = Lat::opp(i);
-    uint32_t r = 0u;
-    if constexpr (kStochastic<S>) {
-      if constexpr (i & 1) {
-        rnd = xorshift32(rnd);
-        r = rnd;
-      } else {
-        r = rnd >> 16;
-      }
-    }
+    const uint32_t r = kStochastic<S> ? (rnd + (uint32_t)i * 0x9E3779B9u) >> 19 : 0u;
     if constexpr (!ODD) {
-      st_mf_r<S, C>(sto, fslot<Lat>(io, (uint32_t)n), h[i], r);
+      st_mf_r<RAW, S, C>(sto, fslot<Lat>(io, (uint32_t)n), h[i], r);
     } else if constexpr (SEP) {
       int dl;
       bool in;
       link_delta<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, td, dl, in);
       const uint32_t e = f1 + (in ? ((uint32_t)(i - 1) << kTileShift) + (uint32_t)dl
                                   : ((uint32_t)(io - 1) << kTileShift));
-      st_mf_r<S, C>(sto, e, h[i], r);
+      st_mf_r<RAW, S, C>(sto, e, h[i], r);
     } else {
       int off;
       bool in;
       link<Lat::e(0, i), Lat::e(1, i), Lat::e(2, i), +1>(nb, off, in);
       const uint32_t e = in ? fslot<Lat>(i, (uint32_t)(n + off)) : fslot<Lat>(io, (uint32_t)n);
-      st_mf_r<S, C>(sto, e, h[i], r);
+      st_mf_r<RAW, S, C>(sto, e, h[i], r);
     }
   });
   st_rs<S, C>(sto, rslot(1, (uint32_t)n), p[0]);
@@ -520,7 +535,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
       st_mg<S, C>(sto, e, v);
     }
   });
-  if constexpr (GEN) scatter_faces<Lat, ODD, S, C>(kp, sto, n, nb, h, p, M, seed);
+  if constexpr (GEN) scatter_faces<Lat, ODD, RAW, S, C>(kp, sto, n, nb, h, p, M, seed);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -588,9 +603,10 @@ __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, 
   constexpr bool kLoadPriority =
       kStochastic<S> || std::is_same<C, double>::value || (!ODD && std::is_same<C, float>::value);
   if constexpr (kLoadPriority) __builtin_amdgcn_s_setprio(1);
-  gather<Lat, ODD, G, S, C, SEP>(kp, state, n, nb, h, p);
+  gather<Lat, ODD, G, S, C, SEP, true>(kp, state, n, nb, h, p);
   if constexpr (kLoadPriority) __builtin_amdgcn_s_setprio(0);
-  const Macro<C> M = macro<Lat, C>(kp, h, p);
+  const Pairs<Lat, C> P = make_pairs<Lat, C>(h);
+  const Macro<C> M = macro<Lat, kFlowScale<S>, C>(kp, P, p);
   LBM_GLOBAL C* sn = gbl(snap);
   if constexpr (MODE == kModeCompare || MODE == kModeSpan) {
     const double ux = M.ux, uy = M.uy, uz = M.uz, T = M.T;
@@ -610,9 +626,9 @@ __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, 
     sn[n + 2 * kp.n] = M.uz;
     sn[n + 3 * kp.n] = M.T;
   }
-  collide_flow<Lat, C>(kp, M, h);
+  collide_flow<Lat, C>(kp, M, P, h);
   collide_heat<C>(kp, M, p);
-  scatter<Lat, ODD, G, S, C, SEP>(kp, state, n, nb, h, p, M, seed);
+  scatter<Lat, ODD, G, S, C, SEP, true>(kp, state, n, nb, h, p, M, seed);
 }
 
 // Node (x, y, z) lies on a face that moves or is open.
@@ -786,7 +802,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_fields(const KParams<C> kp, const
   const Nbr nb = make_nbr(kp, x, y, z);
   C h[Lat::Q], p[7];
   gather<Lat, ODD, true, S, C>(kp, state, n, nb, h, p);
-  const Macro<C> M = macro<Lat, C>(kp, h, p);
+  const Macro<C> M = macro<Lat, 1, C>(kp, make_pairs<Lat, C>(h), p);
   if (rho) rho[m] = 1.0 + (double)M.drho;
   if (ux) ux[m] = (double)M.ux;
   if (uy) uy[m] = (double)M.uy;

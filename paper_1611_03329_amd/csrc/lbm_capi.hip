@@ -339,11 +339,12 @@ static void fill_kparams(const lbm_params* p, const lbm_derived* d, int nodes, i
     for (int i = 0; i < 19; ++i) s[i] = i < 15 ? r[i] : 0.0;
   }
   for (int i = 0; i < 19; ++i) {
-    k->s[i] = (C)s[i];
-    k->sh[i] = (C)(1.0 - 0.5 * s[i]);
+    const int q = p->lattice == 19 ? D3Q19::norm2(i) : (i < 15 ? D3Q15::norm2(i) : 1);
+    k->sn[i] = (C)(s[i] / q);
+    k->shn[i] = (C)((1.0 - 0.5 * s[i]) / q);
   }
   const double z[7] = {p->zeta_T, d->zeta_alpha, d->zeta_alpha, d->zeta_alpha, p->zeta_e, p->zeta_nu, p->zeta_nu};
-  for (int i = 0; i < 7; ++i) k->zeta[i] = (C)z[i];
+  for (int i = 0; i < 7; ++i) k->zeta6[i] = (C)(z[i] / 6.0);
   k->inv_dT = (C)(1.0 / p->delta_T);
 }
 

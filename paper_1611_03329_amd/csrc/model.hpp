@@ -13,7 +13,7 @@
 namespace lbm {
 
 // Kernel parameters: geometry, derived physical constants, relaxation rates and
-// wall rules, in the compute type C.  Passed by value (kernel arguments).
+// wall rules, in the compute type C.  Read in place from the member table.
 template <class C>
 struct KParams {
   int nx, ny, nz;
@@ -40,44 +40,98 @@ struct KParams {
   C gbeta;          // g beta of Eq. 5
   C accel[3];       // a of Eq. 5
   C sigma, inv_sigma, T_ref, varpi;
-  C s[19];          // diagonal of Lambda (Eq. 22 / 16)
-  C sh[19];         // 1 - s_k / 2
-  C zeta[7];        // diagonal of Q (Eq. 38)
+  C sn[19];         // s_k / |M_k|^2: diagonal of Lambda (Eq. 22 / 16) over the row norms of M
+  C shn[19];        // (1 - s_k / 2) / |M_k|^2
+  C zeta6[7];       // diagonal of Q (Eq. 38) over 6 (the common denominator of Eq. 43)
   C inv_dT;         // 1 / delta_T, for theta in the residual
 };
 
-// ------------------------------------------------------------------ macroscopic
-// rho - rho0, T, G, u and F of one node from its shifted pre-collision state.
-template <class C>
-struct Macro {
-  C drho;      // rho - rho0 (Eq. 25)
-  C jx, jy, jz;// sum_i e_i f_i
-  C dsT;       // sigma (T - T_ref) = sum_k p_k (Eq. 39)
-  C T;         // temperature
-  C ux, uy, uz;// Eqs. 27-28
-  C Fx, Fy, Fz;// Eq. 4
+// ------------------------------------------------------------------ flow moments
+// The step kernels may carry the moving flow populations multiplied by a
+// power of two SC (the scale of FP16 storage: the stored values are used as
+// they are) and the rest population too; moments formed from them are SC times
+// the true ones.  Everything that feeds back into the populations (equilibria,
+// forcing) is then formed SC times larger too, from one scaled factor per
+// product, so the collision costs the same as unscaled and no population is
+// scaled on its way in or out.  SC = 1 elsewhere.
+//
+// Pair sums and differences: for the direction i of each opposite pair with
+// the smaller index, s_i = h_i + h_ibar and d_i = h_i - h_ibar.  Even moment
+// rows (rho, e, eps, second- and fourth-order) see only h_0 and the s_i, odd
+// rows (j, q, m) only the d_i.
+template <class Lat, class C>
+struct Pairs {
+  C h0;
+  C s[Lat::Q], d[Lat::Q];  // used at pair representatives only
 };
 
 template <class Lat, class C>
-__device__ __forceinline__ Macro<C> macro(const KParams<C>& kp, const C (&h)[Lat::Q], const C (&p)[7]) {
-  Macro<C> M;
-  C r = C(0), jx = C(0), jy = C(0), jz = C(0);
-  static_for<0, Lat::Q>([&](auto I) {
+__device__ __forceinline__ Pairs<Lat, C> make_pairs(const C (&h)[Lat::Q]) {
+  Pairs<Lat, C> P;
+  P.h0 = h[0];
+  static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    r += h[i];
-    if constexpr (Lat::e(0, i) > 0) jx += h[i];
-    if constexpr (Lat::e(0, i) < 0) jx -= h[i];
-    if constexpr (Lat::e(1, i) > 0) jy += h[i];
-    if constexpr (Lat::e(1, i) < 0) jy -= h[i];
-    if constexpr (Lat::e(2, i) > 0) jz += h[i];
-    if constexpr (Lat::e(2, i) < 0) jz -= h[i];
+    if constexpr (is_pair_rep<Lat>(i)) {
+      P.s[i] = h[i] + h[Lat::opp(i)];
+      P.d[i] = h[i] - h[Lat::opp(i)];
+    }
   });
+  return P;
+}
+
+// Row K of M applied to the populations (Eq. 11), from the pair sums.
+template <class Lat, int K, class C>
+__device__ __forceinline__ C moment(const Pairs<Lat, C>& P) {
+  constexpr bool even = row_is_even<Lat>(K);
+  C m = C(0);
+  bool first = true;
+  if constexpr (even && Lat::moment(K, 0) != 0) {
+    m = Lat::moment(K, 0) == 1 ? P.h0 : C(Lat::moment(K, 0)) * P.h0;
+    first = false;
+  }
+  static_for<1, Lat::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    if constexpr (is_pair_rep<Lat>(i)) {
+      constexpr int c = Lat::moment(K, i);
+      const C v = even ? P.s[i] : P.d[i];
+      if constexpr (c != 0) {
+        if (first) m = c == 1 ? v : (c == -1 ? -v : C(c) * v);
+        else if constexpr (c == 1) m += v;
+        else if constexpr (c == -1) m -= v;
+        else m += C(c) * v;
+        first = false;
+      }
+    }
+  });
+  return m;
+}
+
+// ------------------------------------------------------------------ macroscopic
+// rho - rho0, T, G, u and F of one node from its shifted pre-collision state,
+// and the scaled copies the collision works with.
+template <class C>
+struct Macro {
+  C drho;        // rho - rho0 (Eq. 25)
+  C sdrho;       // SC (rho - rho0)
+  C dsT;         // sigma (T - T_ref) = sum_k p_k (Eq. 39)
+  C T;           // temperature
+  C ux, uy, uz;  // Eqs. 27-28
+  C Ux, Uy, Uz;  // SC u
+  C Fx, Fy, Fz;  // Eq. 4
+  C SFx, SFy, SFz;  // SC F
+};
+
+// SC is the scale of the flow populations (a power of two, exact both ways).
+template <class Lat, int SC, class C>
+__device__ __forceinline__ Macro<C> macro(const KParams<C>& kp, const Pairs<Lat, C>& P, const C (&p)[7]) {
+  constexpr C inv = C(1.0 / SC);
+  Macro<C> M;
+  const C sr = moment<Lat, 0>(P);
+  const C jx = moment<Lat, 3>(P) * inv, jy = moment<Lat, 5>(P) * inv, jz = moment<Lat, 7>(P) * inv;
   C st = C(0);
   static_for<0, 7>([&](auto K) { st += p[decltype(K)::value]; });
-  M.drho = r;
-  M.jx = jx;
-  M.jy = jy;
-  M.jz = jz;
+  M.sdrho = sr;
+  M.drho = sr * inv;
   M.dsT = st;
   M.T = kp.T_ref + st * kp.inv_sigma;
   // Eq. 5 (buoyancy along +gaxis, T0 = T_ref)
@@ -106,35 +160,39 @@ __device__ __forceinline__ Macro<C> macro(const KParams<C>& kp, const C (&h)[Lat
   M.Fx = drag * M.ux + kp.phi * G[0];
   M.Fy = drag * M.uy + kp.phi * G[1];
   M.Fz = drag * M.uz + kp.phi * G[2];
+  constexpr C sc = C(SC);
+  M.Ux = M.ux * sc;
+  M.Uy = M.uy * sc;
+  M.Uz = M.uz * sc;
+  M.SFx = M.Fx * sc;
+  M.SFy = M.Fy * sc;
+  M.SFz = M.Fz * sc;
   return M;
 }
 
 // ------------------------------------------------------------------ equilibria
-// m^eq(rho, u) - m^eq(rho0, 0) row k, rho0 = 1: Eq. 21 (D3Q19, beta = 3, -5.5, -0.5)
-// with the conserved rows rho and rho0 u.
+// SC (m^eq(rho, u) - m^eq(rho0, 0)) row k, rho0 = 1: Eq. 21 (D3Q19, beta = 3,
+// -5.5, -0.5).  Rows 0, 3, 5, 7 (conserved) are not needed: the collision
+// skips row 0 and takes the momentum rows' change from the force directly.
 template <class C>
 __device__ __forceinline__ C meq_shift(D3Q19, int k, const Macro<C>& M, C inv_phi) {
-  const C ux = M.ux, uy = M.uy, uz = M.uz;
-  const C uu = (ux * ux + uy * uy + uz * uz) * inv_phi;
-  const C pxx = (C(2) * ux * ux - uy * uy - uz * uz) * inv_phi;  // 3 p_xx^eq
-  const C pww = (uy * uy - uz * uz) * inv_phi;
+  const C ux = M.ux, uy = M.uy, uz = M.uz, Ux = M.Ux, Uy = M.Uy, Uz = M.Uz;
+  const C uu = (Ux * ux + Uy * uy + Uz * uz) * inv_phi;
+  const C pxx = (C(2) * Ux * ux - Uy * uy - Uz * uz) * inv_phi;  // 3 p_xx^eq
+  const C pww = (Uy * uy - Uz * uz) * inv_phi;
   switch (k) {
-    case 0: return M.drho;
-    case 1: return C(-11) * M.drho + C(19) * uu;
-    case 2: return C(3) * M.drho - C(5.5) * uu;
-    case 3: return ux;
-    case 4: return C(-2.0 / 3.0) * ux;
-    case 5: return uy;
-    case 6: return C(-2.0 / 3.0) * uy;
-    case 7: return uz;
-    case 8: return C(-2.0 / 3.0) * uz;
+    case 1: return C(-11) * M.sdrho + C(19) * uu;
+    case 2: return C(3) * M.sdrho - C(5.5) * uu;
+    case 4: return C(-2.0 / 3.0) * Ux;
+    case 6: return C(-2.0 / 3.0) * Uy;
+    case 8: return C(-2.0 / 3.0) * Uz;
     case 9: return pxx;
     case 10: return C(-0.5) * pxx;
     case 11: return pww;
     case 12: return C(-0.5) * pww;
-    case 13: return ux * uy * inv_phi;
-    case 14: return uy * uz * inv_phi;
-    case 15: return uz * ux * inv_phi;
+    case 13: return Ux * uy * inv_phi;
+    case 14: return Uy * uz * inv_phi;
+    case 15: return Uz * ux * inv_phi;
     default: return C(0);
   }
 }
@@ -142,42 +200,35 @@ __device__ __forceinline__ C meq_shift(D3Q19, int k, const Macro<C>& M, C inv_ph
 // Eq. 15 (D3Q15, beta = 1, -5)
 template <class C>
 __device__ __forceinline__ C meq_shift(D3Q15, int k, const Macro<C>& M, C inv_phi) {
-  const C ux = M.ux, uy = M.uy, uz = M.uz;
-  const C uu = (ux * ux + uy * uy + uz * uz) * inv_phi;
+  const C ux = M.ux, uy = M.uy, uz = M.uz, Ux = M.Ux, Uy = M.Uy, Uz = M.Uz;
+  const C uu = (Ux * ux + Uy * uy + Uz * uz) * inv_phi;
   switch (k) {
-    case 0: return M.drho;
-    case 1: return -M.drho + uu;
-    case 2: return M.drho - C(5) * uu;
-    case 3: return ux;
-    case 4: return C(-7.0 / 3.0) * ux;
-    case 5: return uy;
-    case 6: return C(-7.0 / 3.0) * uy;
-    case 7: return uz;
-    case 8: return C(-7.0 / 3.0) * uz;
-    case 9: return (C(2) * ux * ux - uy * uy - uz * uz) * inv_phi;
-    case 10: return (uy * uy - uz * uz) * inv_phi;
-    case 11: return ux * uy * inv_phi;
-    case 12: return uy * uz * inv_phi;
-    case 13: return uz * ux * inv_phi;
+    case 1: return -M.sdrho + uu;
+    case 2: return M.sdrho - C(5) * uu;
+    case 4: return C(-7.0 / 3.0) * Ux;
+    case 6: return C(-7.0 / 3.0) * Uy;
+    case 8: return C(-7.0 / 3.0) * Uz;
+    case 9: return (C(2) * Ux * ux - Uy * uy - Uz * uz) * inv_phi;
+    case 10: return (Uy * uy - Uz * uz) * inv_phi;
+    case 11: return Ux * uy * inv_phi;
+    case 12: return Uy * uz * inv_phi;
+    case 13: return Uz * ux * inv_phi;
     default: return C(0);
   }
 }
 
-// Forcing moments S~_k, rho0 = 1: Eq. 23 (D3Q19)
+// SC times the forcing moments S~_k, rho0 = 1: Eq. 23 (D3Q19)
 template <class C>
 __device__ __forceinline__ C forcing(D3Q19, int k, const Macro<C>& M, C inv_phi) {
-  const C ux = M.ux, uy = M.uy, uz = M.uz, Fx = M.Fx, Fy = M.Fy, Fz = M.Fz;
+  const C ux = M.ux, uy = M.uy, uz = M.uz, Fx = M.SFx, Fy = M.SFy, Fz = M.SFz;
   const C uF = (ux * Fx + uy * Fy + uz * Fz) * inv_phi;
   const C dxx = (C(2) * ux * Fx - uy * Fy - uz * Fz) * inv_phi;
   const C dww = (uy * Fy - uz * Fz) * inv_phi;
   switch (k) {
     case 1: return C(38) * uF;
     case 2: return C(-11) * uF;
-    case 3: return Fx;
     case 4: return C(-2.0 / 3.0) * Fx;
-    case 5: return Fy;
     case 6: return C(-2.0 / 3.0) * Fy;
-    case 7: return Fz;
     case 8: return C(-2.0 / 3.0) * Fz;
     case 9: return C(2) * dxx;
     case 10: return -dxx;
@@ -193,16 +244,13 @@ __device__ __forceinline__ C forcing(D3Q19, int k, const Macro<C>& M, C inv_phi)
 // Eq. 17 (D3Q15)
 template <class C>
 __device__ __forceinline__ C forcing(D3Q15, int k, const Macro<C>& M, C inv_phi) {
-  const C ux = M.ux, uy = M.uy, uz = M.uz, Fx = M.Fx, Fy = M.Fy, Fz = M.Fz;
+  const C ux = M.ux, uy = M.uy, uz = M.uz, Fx = M.SFx, Fy = M.SFy, Fz = M.SFz;
   const C uF = (ux * Fx + uy * Fy + uz * Fz) * inv_phi;
   switch (k) {
     case 1: return C(2) * uF;
     case 2: return C(-10) * uF;
-    case 3: return Fx;
     case 4: return C(-7.0 / 3.0) * Fx;
-    case 5: return Fy;
     case 6: return C(-7.0 / 3.0) * Fy;
-    case 7: return Fz;
     case 8: return C(-7.0 / 3.0) * Fz;
     case 9: return C(2) * (C(2) * ux * Fx - uy * Fy - uz * Fz) * inv_phi;
     case 10: return C(2) * (uy * Fy - uz * Fz) * inv_phi;
@@ -218,41 +266,29 @@ __device__ __forceinline__ C forcing(D3Q15, int k, const Macro<C>& M, C inv_phi)
 //   dm_k = (M h)_k - (m^eq_k - m^eq_k(rest)),
 //   delta_k = -s_k dm_k + (1 - s_k/2) S~_k,
 //   h*_i = h_i + sum_k M_ki delta_k / |M_k|^2          (M^-1 = M^T diag(1/|M_k|^2)).
-// Row 0 has dm_0 = 0 and S~_0 = 0, so it is skipped.  Both products use the
-// symmetry of the basis: with s_i = h_i + h_ibar and d_i = h_i - h_ibar for one
-// direction i of each opposite pair, even rows of M see only h_0 and the s_i,
-// odd rows only the d_i; on the way back h*_i and h*_ibar share the even part
-// and differ in the sign of the odd part.
+// Row 0 has dm_0 = 0 and S~_0 = 0, so it is skipped.  The momentum rows 3, 5, 7
+// need no moment either: their equilibrium is rho0 u and the closure of Eqs.
+// 26-28 makes rho0 u = j + F/2, so delta = -s_j (-F/2) + (1 - s_j/2) F = F for
+// every s_j (the momentum gains rho0 F per step).  The other moments come from
+// the pair sums P (make_pairs); on the way back h*_i and h*_ibar share the
+// even part of the update and differ in the sign of the odd part.
 template <class Lat, class C>
-__device__ __forceinline__ void collide_flow(const KParams<C>& kp, const Macro<C>& M, C (&h)[Lat::Q]) {
+__device__ __forceinline__ void collide_flow(const KParams<C>& kp, const Macro<C>& M, const Pairs<Lat, C>& P,
+                                             C (&h)[Lat::Q]) {
   constexpr int Q = Lat::Q;
-  C sp[Q], dp[Q];  // used at pair representatives only
-  static_for<1, Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    if constexpr (is_pair_rep<Lat>(i)) {
-      sp[i] = h[i] + h[Lat::opp(i)];
-      dp[i] = h[i] - h[Lat::opp(i)];
-    }
-  });
   C d[Q];
   static_for<1, Q>([&](auto K) {
     constexpr int k = decltype(K)::value;
-    constexpr bool even = row_is_even<Lat>(k);
-    C m = C(0);
-    if constexpr (even && Lat::moment(k, 0) != 0) m = C(Lat::moment(k, 0)) * h[0];
-    static_for<1, Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      if constexpr (is_pair_rep<Lat>(i)) {
-        constexpr int c = Lat::moment(k, i);
-        const C v = even ? sp[i] : dp[i];
-        if constexpr (c == 1) m += v;
-        else if constexpr (c == -1) m -= v;
-        else if constexpr (c != 0) m += C(c) * v;
-      }
-    });
-    const C dm = m - meq_shift(Lat{}, k, M, kp.inv_phi);
-    const C delta = -kp.s[k] * dm + kp.sh[k] * forcing(Lat{}, k, M, kp.inv_phi);
-    d[k] = delta * C(1.0 / Lat::norm2(k));
+    if constexpr (k == 3) {
+      d[k] = M.SFx * C(1.0 / Lat::norm2(k));
+    } else if constexpr (k == 5) {
+      d[k] = M.SFy * C(1.0 / Lat::norm2(k));
+    } else if constexpr (k == 7) {
+      d[k] = M.SFz * C(1.0 / Lat::norm2(k));
+    } else {
+      const C dm = moment<Lat, k>(P) - meq_shift(Lat{}, k, M, kp.inv_phi);
+      d[k] = kp.shn[k] * forcing(Lat{}, k, M, kp.inv_phi) - kp.sn[k] * dm;
+    }
   });
   // rest population: even rows only
   {
@@ -308,7 +344,7 @@ __device__ __forceinline__ void collide_heat(const KParams<C>& kp, const Macro<C
     if constexpr (k == 2) eq = M.T * M.uy;
     if constexpr (k == 3) eq = M.T * M.uz;
     if constexpr (k == 4) eq = kp.varpi * M.dsT;
-    d[k] = -kp.zeta[k] * (m - eq) * C(1.0 / 6.0);
+    d[k] = -kp.zeta6[k] * (m - eq);
   });
   static_for<0, 7>([&](auto I) {
     constexpr int i = decltype(I)::value;
