@@ -306,34 +306,6 @@ constexpr int d3q7_face() {
   return 2 * a + (e * SG > 0 ? 1 : 0);
 }
 
-// ------------------------------------------------------------------ x staging
-// Populations that move along x land one node over, one element off the node
-// that computed them: stored straight from there, the 64 lanes of a wavefront
-// write 64 elements that straddle one more 128-byte line than they fill, and
-// neighbouring wavefronts share the partial lines.  The x-staged odd step (XS)
-// puts every x-moving post-collision value into LDS first; after a block
-// barrier each thread stores the value of its x-neighbour at its own x
-// position, so the wavefront's store covers whole, aligned lines.  Only values
-// that cross the block's edge (or wrap around a periodic x axis) and the
-// bounce-backs are stored by the node that computed them.
-//
-// Slot in the staging array of flow population i (-1: no x component); the
-// two D3Q7 x populations follow the flow ones.
-template <class Lat>
-constexpr int x_slot(int i) {
-  int j = 0;
-  for (int k = 1; k < i; ++k) j += Lat::e(0, k) != 0 ? 1 : 0;
-  return Lat::e(0, i) != 0 ? j : -1;
-}
-template <class Lat>
-constexpr int x_count() {
-  int j = 0;
-  for (int k = 1; k < Lat::Q; ++k) j += Lat::e(0, k) != 0 ? 1 : 0;
-  return j;
-}
-template <class Lat>
-constexpr int kXStage = x_count<Lat>() + 2;
-
 template <class Lat, int J>
 __host__ __device__ constexpr double weight() {
   if constexpr (Lat::Q == 19) return Lat::w36(J) / 36.0;
@@ -512,94 +484,10 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n
 // ------------------------------------------------------------------ scatter
 // Post-collision shifted populations of node n, written for the next parity.
 // M holds the node's macroscopic state (used by the open-face rules).
-// Store of a staged moving flow population (already an FP16 number with FP16
-// storage, so the conversion is exact).
-template <class S, class C>
-__device__ __forceinline__ void st_mf_staged(const S& s, uint32_t e, C v) {
-  if constexpr (kStochastic<S>) {
-    LBM_GLOBAL char* b = (LBM_GLOBAL char*)s.mf;
-    *(LBM_GLOBAL _Float16*)(b + e * 2u) = (_Float16)(float)v;
-  } else {
-    st_mf<S, C>(s, e, v);
-  }
-}
-
-// Second half of the x-staged odd scatter (XS), after the block barrier: the
-// x-moving populations of node n (lean wall rules), from the staging array xs
-// (x population j of the block's thread t at xs[j * kMaxBlock + t]).  A thread
-// stores its x-neighbour's value when that neighbour is in the block and in
-// the same row (no periodic wrap), and its own value when it leaves the box
-// (bounce-back, thermal wall rule) or no thread of the block stores it.
-template <class Lat, class S, class C, bool SEP>
-__device__ __forceinline__ void scatter_x(const KParams<C>& kp, const S& sto, int n, int x, const Nbr& nb,
-                                          const C* xs) {
-  const int t = (int)threadIdx.x, B = (int)blockDim.x;
-  // neighbour along -x / +x: in the block and in the same row
-  const bool lo = t > 0 && x > 0, hi = t < B - 1 && x < kp.nx - 1;
-  const uint32_t f1 = fslot<Lat>(1, (uint32_t)n);
-  int td[3][2];
-  if constexpr (SEP) tile_deltas<Lat>(nb, n, f1, td);
-  static_for<1, Lat::Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    constexpr int ex = Lat::e(0, i), ey = Lat::e(1, i), ez = Lat::e(2, i);
-    if constexpr (ex != 0) {
-      constexpr int io = Lat::opp(i);
-      constexpr int j = x_slot<Lat>(i);
-      const bool recv = ex > 0 ? lo : hi;      // the sender x - ex is staged here
-      const bool handled = ex > 0 ? hi : lo;   // the receiver x + ex stores this node's value
-      // the link's y and z parts (same for the sender: same row)
-      bool inyz;
-      uint32_t eA;
-      if constexpr (SEP) {
-        int dl;
-        link_delta<0, ey, ez, +1>(nb, td, dl, inyz);
-        eA = f1 + ((uint32_t)(i - 1) << kTileShift) + (uint32_t)dl;
-      } else {
-        int off;
-        link<0, ey, ez, +1>(nb, off, inyz);
-        eA = fslot<Lat>(i, (uint32_t)(n + off));
-      }
-      if (recv && inyz) st_mf_staged<S, C>(sto, eA, xs[j * kMaxBlock + t - ex]);
-      bool in;
-      uint32_t eB;
-      if constexpr (SEP) {
-        int dl;
-        link_delta<ex, ey, ez, +1>(nb, td, dl, in);
-        eB = f1 + (in ? ((uint32_t)(i - 1) << kTileShift) + (uint32_t)dl : ((uint32_t)(io - 1) << kTileShift));
-      } else {
-        int off;
-        link<ex, ey, ez, +1>(nb, off, in);
-        eB = in ? fslot<Lat>(i, (uint32_t)(n + off)) : fslot<Lat>(io, (uint32_t)n);
-      }
-      if (!in || !handled) st_mf_staged<S, C>(sto, eB, xs[j * kMaxBlock + t]);
-    }
-  });
-  static_for<1, 3>([&](auto K) {
-    constexpr int k = decltype(K)::value;  // D3Q7 +x (1) and -x (2)
-    constexpr int ex = D3Q7::e(0, k);
-    constexpr int ko = D3Q7::opp(k);
-    constexpr int j = x_count<Lat>() + k - 1;
-    const bool recv = ex > 0 ? lo : hi;
-    const bool handled = ex > 0 ? hi : lo;
-    if (recv) st_mg<S, C>(sto, gslot(k, (uint32_t)n), xs[j * kMaxBlock + t - ex]);
-    int off;
-    bool in;
-    link<ex, 0, 0, +1>(nb, off, in);
-    constexpr int fc = d3q7_face<k, +1>();
-    const C own = xs[j * kMaxBlock + t];
-    if (!in) st_mg<S, C>(sto, gslot(ko, (uint32_t)n), kp.heat_a[fc] * own + kp.heat_b[fc]);
-    else if (!handled) st_mg<S, C>(sto, gslot(k, (uint32_t)(n + off)), own);
-  });
-}
-
-// RAW (the step kernels): h comes in times kFlowScale<S>.  XS (odd step, lean
-// rules): the x-moving populations go to the staging array xs instead, for
-// scatter_x after the block barrier.
-template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false, bool RAW = false, bool XS = false>
+// RAW (the step kernels): h comes in times kFlowScale<S>.
+template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false, bool RAW = false>
 __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
-                                        const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M, uint32_t seed,
-                                        C* xs = nullptr) {
-  static_assert(!XS || (ODD && !GEN && RAW), "x staging is built for the lean odd step");
+                                        const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M, uint32_t seed) {
   constexpr int SC = RAW ? kFlowScale<S> : 1;
   st_rs<S, C>(sto, rslot(0, (uint32_t)n), h[0] * C(1.0 / SC));
   // random bits for the stochastic FP16 rounding: one hashed word per node and
@@ -614,13 +502,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
     constexpr int i = decltype(I)::value;
     constexpr int io = Lat::opp(i);
     const uint32_t r = kStochastic<S> ? (rnd + (uint32_t)i * 0x9E3779B9u) >> 19 : 0u;
-    if constexpr (XS && Lat::e(0, i) != 0) {
-      // FP16 storage: rounded here, with this node's bits, whichever thread
-      // stores it (the result does not depend on the block size)
-      C v = h[i];
-      if constexpr (kStochastic<S>) v = (C)(float)half_sr((float)h[i], r);
-      xs[x_slot<Lat>(i) * kMaxBlock + (int)threadIdx.x] = v;
-    } else if constexpr (!ODD) {
+    if constexpr (!ODD) {
       st_mf_r<RAW, S, C>(sto, fslot<Lat>(io, (uint32_t)n), h[i], r);
     } else if constexpr (SEP) {
       int dl;
@@ -641,9 +523,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int ko = D3Q7::opp(k);
-    if constexpr (XS && D3Q7::e(0, k) != 0) {
-      xs[(x_count<Lat>() + k - 1) * kMaxBlock + (int)threadIdx.x] = p[k];
-    } else if constexpr (!ODD) {
+    if constexpr (!ODD) {
       st_mg<S, C>(sto, gslot(ko, (uint32_t)n), p[k]);
     } else {
       int off;
@@ -711,9 +591,9 @@ constexpr int kPartStride = 8;  // doubles per block in the partials buffer
 // The per-node body of a step: gather, moments, residual bookkeeping,
 // collisions, scatter.  G selects the general wall rules; seed (a hash of the
 // lattice's step count) drives the stochastic rounding of FP16 storage.
-template <class Lat, class S, class C, bool ODD, int MODE, bool G, bool SEP = false, bool XS = false>
+template <class Lat, class S, class C, bool ODD, int MODE, bool G, bool SEP = false>
 __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, C* __restrict__ snap, int n,
-                                          const Nbr& nb, double (&red)[5], uint32_t seed, C* xs = nullptr) {
+                                          const Nbr& nb, double (&red)[5], uint32_t seed) {
   C h[Lat::Q], p[7];
   // A wavefront that is issuing its loads goes before wavefronts that are
   // computing, so the loads of the next wavefronts are in flight sooner.
@@ -748,7 +628,7 @@ __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, 
   }
   collide_flow<Lat, C>(kp, M, P, h);
   collide_heat<C>(kp, M, p);
-  scatter<Lat, ODD, G, S, C, SEP, true, XS>(kp, state, n, nb, h, p, M, seed, xs);
+  scatter<Lat, ODD, G, S, C, SEP, true>(kp, state, n, nb, h, p, M, seed);
 }
 
 // Node (x, y, z) lies on a face that moves or is open.
@@ -774,23 +654,7 @@ __device__ __forceinline__ void step_block(const KParams<C>& kp, const S& state,
                                            double* __restrict__ part, int lb, uint32_t seed) {
   const int n = lb * blockDim.x + threadIdx.x;
   double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  // the lean odd step with FP32 arithmetic stages its x-moving populations
-  constexpr bool XS = ODD && !GEN && std::is_same<C, float>::value;
-  if constexpr (XS) {
-    __shared__ C xs[kXStage<Lat> * kMaxBlock];
-    const bool act = n < kp.n;
-    int x = 0, y = 0, z = 0;
-    Nbr nb{};
-    if (act) {
-      node_coords(kp, n, x, y, z);
-      nb = make_nbr(kp, x, y, z);
-      step_node<Lat, S, C, ODD, MODE, false, SEP, true>(kp, state, snap, n, nb, red, seed, xs);
-    }
-    __syncthreads();
-    if (act) scatter_x<Lat, S, C, SEP>(kp, state, n, x, nb, xs);
-    // the next tile of a persistent block writes the array again
-    __syncthreads();
-  } else if (n < kp.n) {
+  if (n < kp.n) {
     int x, y, z;
     node_coords(kp, n, x, y, z);
     const Nbr nb = make_nbr(kp, x, y, z);
