@@ -495,9 +495,8 @@ def main(argv=None) -> int:
     ap.add_argument("--tune-count", type=int, default=16, help="solves: workloads used to tune the launch shape")
     ap.add_argument("--smallest-first-mnodes", type=float, default=4.0,
                     help="solves: resident-node cap (millions) of the smallest-first serving run")
-    ap.add_argument("--precision", choices=("fp32", "fp16", "fp16all"), default="fp32",
-                    help="cavity256: population storage (fp16: FP16 flow populations; fp16all: every "
-                         "population in FP16; FP32 arithmetic)")
+    ap.add_argument("--precision", choices=("fp32", "fp16"), default="fp32",
+                    help="cavity256: population storage (FP16 flow populations, FP32 arithmetic)")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--check-interval", type=int, default=100)
@@ -586,9 +585,9 @@ def main(argv=None) -> int:
           f"({checks} checks timed), Nu_hot {nu[0]:.5f}", file=sys.stderr, flush=True)
 
     fp16 = args.precision == "fp16"
-    bytes_per_node = {"fp32": 2 * 26 * 4, "fp16": 2 * (18 * 2 + 8 * 4), "fp16all": 2 * 26 * 2}[args.precision]
+    bytes_per_node = 2 * (18 * 2 + 8 * 4) if fp16 else 2 * (19 + 7) * 4
     achieved = bytes_per_node * nodes / (ms_per_step / 1e3) / 1e9
-    traffic = traffic_from_profiles(nodes) if args.precision == "fp32" else None
+    traffic = None if fp16 else traffic_from_profiles(nodes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
                 "copy_reference_GBps": None if copy_gbps is None else round(copy_gbps, 1)}
@@ -627,10 +626,7 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {
             "workload": "porous cavity 256^3, D3Q19 MRT flow + D3Q7 MRT temperature, "
-                        + {"fp32": "FP32, ",
-                           "fp16": "FP16 flow storage (stochastic rounding), FP32 arithmetic, ",
-                           "fp16all": "FP16 storage of every population (stochastic rounding), FP32 arithmetic, "
-                           }[args.precision]
+                        + ("FP16 flow storage (stochastic rounding), FP32 arithmetic, " if fp16 else "FP32, ")
                         + "phi 0.4, Da 1e-4, Ra 1e6, Pr 1, seed 2"
                         + (f", residual check every {K} steps ({checks} in the timed region)" if checks else
                            ", no residual check in the timed region"),

@@ -79,13 +79,11 @@ typedef enum {
 typedef enum {
   LBM_FP64 = 0,        /* populations stored and computed in FP64 */
   LBM_FP32 = 1,        /* populations stored and computed in FP32 */
-  LBM_FP16_STORAGE = 2, /* moving flow populations stored in FP16; temperature and rest
-                           populations in FP32; arithmetic in FP32.  The FP16 stores round
-                           stochastically (zero-mean error) with random bits hashed from the
-                           lattice's step count, node and population: reproducible runs */
-  LBM_FP16_ALL = 3      /* every population stored in FP16, rounded as above; arithmetic in
-                           FP32 (104 instead of 136 bytes per node and step for D3Q19) */
-} lbm_precision;        /* in every mode populations are stored shifted by their rest state */
+  LBM_FP16_STORAGE = 2 /* moving flow populations stored in FP16; temperature and rest
+                          populations in FP32; arithmetic in FP32.  The FP16 stores round
+                          stochastically (zero-mean error) with random bits hashed from the
+                          lattice's step count, node and population: reproducible runs */
+} lbm_precision;       /* in every mode populations are stored shifted by their rest state */
 
 /* Face rules.  WALL: halfway bounce-back (u_wall: moving wall; a wall velocity
  * with a normal component makes the face an inlet).  OUTLET: open boundary at

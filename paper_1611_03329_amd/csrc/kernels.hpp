@@ -78,12 +78,11 @@ __device__ __forceinline__ C ld_raw(const S* base, uint32_t e) {
 
 // Population storage in three regions: the moving flow populations f_1..f_{Q-1}
 // (type Mf), the moving temperature populations g_1..g_6 (type Mg) and the two
-// rest populations f_0, g_0 (type Rs), which never leave their node.  In the
-// FP16 storage mode only the moving flow populations are FP16: the heat flux
-// is carried by the difference of opposite g populations, far below FP16's
-// resolution of each of them, and the rest populations change only through
-// the collision, by amounts FP16 would round away.  The all-FP16 mode stores
-// every population in FP16 (times kHalfScale, rounded stochastically).
+// rest populations f_0, g_0 (type Rs), which never leave their node.  With FP16
+// storage only the moving flow populations are FP16: the heat flux is carried
+// by the difference of opposite g populations, far below FP16's resolution of
+// each of them, and the rest populations change only through the collision, by
+// amounts FP16 would round away.
 template <class Mf, class Mg, class Rs>
 struct Store {
   using MoveF = Mf;
@@ -163,19 +162,6 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 __device__ __forceinline__ _Float16 half_sr(float f, uint32_t r13) {
   const uint32_t u = __float_as_uint(f);
   return (_Float16)__uint_as_float((u + r13) & ~0x1FFFu);
-}
-
-// Store of a temperature or rest population (given true): with FP16 storage of
-// every population r13 drives the rounding as for the flow populations.
-template <class T, class C>
-__device__ __forceinline__ void st_sr(T* base, uint32_t e, C v, uint32_t r13) {
-  if constexpr (std::is_same<T, _Float16>::value) {
-    LBM_GLOBAL char* b = (LBM_GLOBAL char*)base;
-    *(LBM_GLOBAL _Float16*)(b + e * 2u) = half_sr((float)v * kHalfScale, r13);
-  } else {
-    (void)r13;
-    st<T, C>(base, e, v);
-  }
 }
 
 // Store of a moving flow population given as the step carries it (RAW: times
@@ -428,11 +414,7 @@ __device__ __forceinline__ void scatter_faces(const KParams<C>& kp, const S& sto
       static_for<1, 7>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if constexpr (d3q7_face<k, +1>() == f) {
-          if (on) {
-            const uint32_t r = mix32(seed + (uint32_t)n * 0x9E3779B9u + (uint32_t)(Lat::Q + k) * 0x85EBCA6Bu);
-            st_sr<typename S::MoveG, C>(sto.mg, gslot(D3Q7::opp(k), (uint32_t)n), open_heat_value<C>(kp, p[k], M),
-                                        r >> 19);
-          }
+          if (on) st_mg<S, C>(sto, gslot(D3Q7::opp(k), (uint32_t)n), open_heat_value<C>(kp, p[k], M));
         }
       });
     }
@@ -507,21 +489,19 @@ template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false, boo
 __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                         const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M, uint32_t seed) {
   constexpr int SC = RAW ? kFlowScale<S> : 1;
+  st_rs<S, C>(sto, rslot(0, (uint32_t)n), h[0] * C(1.0 / SC));
   // random bits for the stochastic FP16 rounding: one hashed word per node and
   // step, and for population i the top 13 bits of that word plus i times the
   // golden-ratio constant (a Weyl sequence): each population's bits are
   // uniform, and the node's populations take evenly spread rotations of them
-  // (f_0 takes i = 0, the temperature populations i = Q + k)
   const uint32_t rnd = kStochastic<S> ? mix32(seed + (uint32_t)n) : 0u;
-  auto bits = [&](int i) -> uint32_t { return kStochastic<S> ? (rnd + (uint32_t)i * 0x9E3779B9u) >> 19 : 0u; };
-  st_sr<typename S::Rest, C>(sto.rs, rslot(0, (uint32_t)n), h[0] * C(1.0 / SC), bits(0));
   const uint32_t f1 = fslot<Lat>(1, (uint32_t)n);
   int td[3][2];
   if constexpr (ODD && SEP) tile_deltas<Lat>(nb, n, f1, td);
   static_for<1, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int io = Lat::opp(i);
-    const uint32_t r = bits(i);
+    const uint32_t r = kStochastic<S> ? (rnd + (uint32_t)i * 0x9E3779B9u) >> 19 : 0u;
     if constexpr (!ODD) {
       st_mf_r<RAW, S, C>(sto, fslot<Lat>(io, (uint32_t)n), h[i], r);
     } else if constexpr (SEP) {
@@ -539,12 +519,12 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
       st_mf_r<RAW, S, C>(sto, e, h[i], r);
     }
   });
-  st_sr<typename S::Rest, C>(sto.rs, rslot(1, (uint32_t)n), p[0], bits(Lat::Q));
+  st_rs<S, C>(sto, rslot(1, (uint32_t)n), p[0]);
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int ko = D3Q7::opp(k);
     if constexpr (!ODD) {
-      st_sr<typename S::MoveG, C>(sto.mg, gslot(ko, (uint32_t)n), p[k], bits(Lat::Q + k));
+      st_mg<S, C>(sto, gslot(ko, (uint32_t)n), p[k]);
     } else {
       int off;
       bool in;
@@ -552,7 +532,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
       constexpr int fc = d3q7_face<k, +1>();
       const C v = in ? p[k] : kp.heat_a[fc] * p[k] + kp.heat_b[fc];
       const uint32_t e = in ? gslot(k, (uint32_t)(n + off)) : gslot(ko, (uint32_t)n);
-      st_sr<typename S::MoveG, C>(sto.mg, e, v, bits(Lat::Q + k));
+      st_mg<S, C>(sto, e, v);
     }
   });
   if constexpr (GEN) scatter_faces<Lat, ODD, RAW, S, C>(kp, sto, n, nb, h, p, M, seed);

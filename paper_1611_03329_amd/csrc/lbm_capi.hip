@@ -189,8 +189,7 @@ static lbm_status derive(const lbm_params* p, lbm_derived* d) {
   if (p->energy != LBM_ENERGY_TEMPERATURE) return fail(LBM_ERR_UNSUPPORTED, "energy model %d", p->energy);
   if (p->lattice != 19 && p->lattice != 15)
     return fail(LBM_ERR_INVALID_ARG, "lattice must be 19 or 15 (got %d)", p->lattice);
-  if (p->precision != LBM_FP64 && p->precision != LBM_FP32 && p->precision != LBM_FP16_STORAGE &&
-      p->precision != LBM_FP16_ALL)
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32 && p->precision != LBM_FP16_STORAGE)
     return fail(LBM_ERR_UNSUPPORTED, "precision %d is not supported", p->precision);
   if (p->nx < 1 || p->ny < 1 || p->nz < 1)
     return fail(LBM_ERR_INVALID_ARG, "box %dx%dx%d must have at least one node per axis", p->nx, p->ny, p->nz);
@@ -199,7 +198,7 @@ static lbm_status derive(const lbm_params* p, lbm_derived* d) {
     return fail(LBM_ERR_INVALID_ARG, "box of %lld nodes exceeds the 2^30 node limit", nodes);
   {
     const long long sb = p->precision == LBM_FP64 ? 8 : (p->precision == LBM_FP32 ? 4 : 2);
-    const long long sg = p->precision == LBM_FP64 ? 8 : (p->precision == LBM_FP16_ALL ? 2 : 4);
+    const long long sg = p->precision == LBM_FP64 ? 8 : 4;
     const long long per_plane = (nodes + kTile - 1) / kTile * kTile;
     if ((long long)(p->lattice - 1) * per_plane * sb >= (1ll << 32) || 6ll * per_plane * sg >= (1ll << 32))
       return fail(LBM_ERR_UNSUPPORTED, "each population region of one lattice must fit in 4 GiB (%lld nodes)",
@@ -392,8 +391,7 @@ static Layout layout(const lbm_params* p) {
   Layout L;
   const long long nodes = (long long)p->nx * p->ny * p->nz;
   const size_t s = p->precision == LBM_FP64 ? 8 : (p->precision == LBM_FP32 ? 4 : 2);  // moving f
-  const size_t c = p->precision == LBM_FP64 ? 8 : 4;  // compute type (the check snapshot)
-  const size_t g = p->precision == LBM_FP16_ALL ? 2 : c;  // moving g and rest populations
+  const size_t c = p->precision == LBM_FP64 ? 8 : 4;  // moving g, rest populations, compute type
   const bool enth = p->energy == LBM_ENERGY_ENTHALPY;  // no flow populations, no check snapshot
   // The FP64 flow step (2-3 wavefronts per SIMD) measured 3-4 % faster with
   // 128-thread blocks on 256^3 boxes of either lattice and 2 % on a D3Q19
@@ -407,9 +405,9 @@ static Layout layout(const lbm_params* p) {
   L.mf = off;
   off += enth ? 0 : align_up((size_t)(p->lattice - 1) * L.pstride * s, 256);
   L.mg = off;
-  off += align_up((size_t)6 * L.pstride * g, 256);
+  off += align_up((size_t)6 * L.pstride * c, 256);
   L.rs = off;
-  off += align_up((size_t)2 * L.pstride * g, 256);
+  off += align_up((size_t)2 * L.pstride * c, 256);
   L.snap = off;
   off += enth ? 0 : align_up((size_t)4 * nodes * c, 256);
   L.part = off;
@@ -446,17 +444,14 @@ static void with_types(const lbm_lattice* h, F&& f) {
   using S64 = Store<double, double, double>;
   using S32 = Store<float, float, float>;
   using S16 = Store<_Float16, float, float>;
-  using S16A = Store<_Float16, _Float16, _Float16>;
   if (h->q == 19) {
     if (h->prec == LBM_FP64) f(D3Q19{}, S64{}, double{}, h->kd);
     else if (h->prec == LBM_FP32) f(D3Q19{}, S32{}, float{}, h->kf);
-    else if (h->prec == LBM_FP16_STORAGE) f(D3Q19{}, S16{}, float{}, h->kf);
-    else f(D3Q19{}, S16A{}, float{}, h->kf);
+    else f(D3Q19{}, S16{}, float{}, h->kf);
   } else {
     if (h->prec == LBM_FP64) f(D3Q15{}, S64{}, double{}, h->kd);
     else if (h->prec == LBM_FP32) f(D3Q15{}, S32{}, float{}, h->kf);
-    else if (h->prec == LBM_FP16_STORAGE) f(D3Q15{}, S16{}, float{}, h->kf);
-    else f(D3Q15{}, S16A{}, float{}, h->kf);
+    else f(D3Q15{}, S16{}, float{}, h->kf);
   }
 }
 
@@ -1282,8 +1277,7 @@ static bool member_general(const lbm_lattice* h) {
 // Launch variant of member h: bit 0 the general wall rules, bit 1 separable
 // tiles with FP16 storage (its odd step takes the SEP kernel).
 static int member_variant(const lbm_lattice* h) {
-  const bool half = h->prec == LBM_FP16_STORAGE || h->prec == LBM_FP16_ALL;
-  return (member_general(h) ? 1 : 0) | (half && h->kf.sep ? 2 : 0);
+  return (member_general(h) ? 1 : 0) | (h->prec == LBM_FP16_STORAGE && h->kf.sep ? 2 : 0);
 }
 
 // Bytes of populations a step streams for member h.
@@ -1291,7 +1285,6 @@ static uint64_t member_state_bytes(const lbm_lattice* h) {
   const uint64_t ps = (uint64_t)h->pstride;
   if (h->prec == LBM_FP64) return ps * 8u * (uint64_t)(h->q + 7);
   if (h->prec == LBM_FP32) return ps * 4u * (uint64_t)(h->q + 7);
-  if (h->prec == LBM_FP16_ALL) return ps * 2u * (uint64_t)(h->q + 7);
   return ps * (2u * (uint64_t)(h->q - 1) + 4u * 8u);
 }
 
@@ -1421,17 +1414,14 @@ static void batch_types(const lbm_batch* b, F&& f) {
   using S64 = Store<double, double, double>;
   using S32 = Store<float, float, float>;
   using S16 = Store<_Float16, float, float>;
-  using S16A = Store<_Float16, _Float16, _Float16>;
   if (b->q == 19) {
     if (b->prec == LBM_FP64) f(D3Q19{}, S64{}, double{});
     else if (b->prec == LBM_FP32) f(D3Q19{}, S32{}, float{});
-    else if (b->prec == LBM_FP16_STORAGE) f(D3Q19{}, S16{}, float{});
-    else f(D3Q19{}, S16A{}, float{});
+    else f(D3Q19{}, S16{}, float{});
   } else {
     if (b->prec == LBM_FP64) f(D3Q15{}, S64{}, double{});
     else if (b->prec == LBM_FP32) f(D3Q15{}, S32{}, float{});
-    else if (b->prec == LBM_FP16_STORAGE) f(D3Q15{}, S16{}, float{});
-    else f(D3Q15{}, S16A{}, float{});
+    else f(D3Q15{}, S16{}, float{});
   }
 }
 

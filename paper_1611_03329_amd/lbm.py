@@ -26,8 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 FP64 = 0
 FP32 = 1
 FP16_STORAGE = 2
-FP16_ALL = 3
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_STORAGE, "fp16all": FP16_ALL}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16_STORAGE}
 ENERGY = {"temperature": 0, "enthalpy": 1}
 FLOW = {"periodic": 0, "wall": 1, "outlet": 3}
 HEAT = {"periodic": 0, "adiabatic": 1, "isothermal": 2, "outflow": 3}
