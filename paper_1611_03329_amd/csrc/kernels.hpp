@@ -847,28 +847,32 @@ __global__ void __launch_bounds__(kMaxBlock) k_sum_final(const double* __restric
   }
 }
 
-// Heat entering through each isothermal face during the last streaming:
-// one block per face, FP64 sum of 2 g_k - 2 omega_k sigma T_w over the face's
-// wall nodes, k the population entering the fluid.  out[face] = that sum.
-// The wall term 2 omega_k sigma T_w is taken as the step applies it, in the
-// step's precision: the sum is then exactly the heat the discrete model
-// exchanges with the wall.  (At Ra = 1e6 the flux per node is about 1/700 of
-// a population, and the FP32 rounding of the wall term alone would move Nu by
+// Heat entering through each isothermal face during the last streaming, in
+// two deterministic stages.  k_wall_flux: block (b, f) sums, in FP64, 2 g_k -
+// 2 omega_k sigma T_w over chunk b (of gridDim.x equal chunks) of face f's
+// wall nodes, k the population entering the fluid, into part[f * gridDim.x +
+// b]; k_wall_fold adds each face's chunk sums in order into out[face].  The
+// wall term 2 omega_k sigma T_w is taken as the step applies it, in the step's
+// precision: the sum is then exactly the heat the discrete model exchanges
+// with the wall.  (At Ra = 1e6 the flux per node is about 1/700 of a
+// population, and the FP32 rounding of the wall term alone would move Nu by
 // 4e-5.)
 template <class Lat, class S, class C, bool ODD>
 __global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, const S state,
                                                          const int* __restrict__ isothermal,
-                                                         double* __restrict__ out) {
-  const int face = blockIdx.x;
+                                                         double* __restrict__ part) {
+  const int face = blockIdx.y;
   const int a = face >> 1, side = face & 1;
   const int dim[3] = {kp.nx, kp.ny, kp.nz};
   const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
   const int cnt = dim[a1] * dim[a2];
+  const int per = (cnt + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int m0 = (int)blockIdx.x * per, m1 = min(cnt, m0 + per);
   double v[1] = {0.0};
   if (isothermal[face]) {
     const int k = 1 + 2 * a + side;  // D3Q7 direction pointing into the fluid
     const double shift = (double)kp.heat_b[face];
-    for (int m = threadIdx.x; m < cnt; m += blockDim.x) {
+    for (int m = m0 + (int)threadIdx.x; m < m1; m += blockDim.x) {
       int c[3];
       c[a] = side ? dim[a] - 1 : 0;
       c[a1] = m % dim[a1];
@@ -885,7 +889,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_wall_flux(const KParams<C> kp, co
     }
   }
   block_reduce<1>(v, 0u);
-  if (threadIdx.x == 0) out[face] = v[0];
+  if (threadIdx.x == 0) part[face * (int)gridDim.x + (int)blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(64) k_wall_fold(const double* __restrict__ part, int chunks,
+                                                  double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < chunks; ++b) s += part[blockIdx.x * chunks + b];
+  out[blockIdx.x] = s;
 }
 
 // ------------------------------------------------------------------ state I/O

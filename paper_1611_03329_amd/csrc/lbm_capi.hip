@@ -395,8 +395,9 @@ static Layout layout(const lbm_params* p) {
   const bool enth = p->energy == LBM_ENERGY_ENTHALPY;  // no flow populations, no check snapshot
   // The FP64 flow step (2-3 wavefronts per SIMD) measured 3-4 % faster with
   // 128-thread blocks on 256^3 boxes of either lattice and 2 % on a D3Q19
-  // channel, 1.5 % slower on the D3Q15 channel.  Lattices under 2^20 nodes,
-  // whose steps are launch latency, and the other steps take 256.
+  // channel, 1.5 % slower on the D3Q15 channel; the rule stays by size alone
+  // (a D3Q15 cavity gains 4 %).  Lattices under 2^20 nodes, whose steps are
+  // launch latency, and the other steps take 256.
   L.block = (p->precision == LBM_FP64 && !enth && nodes >= (1LL << 20)) ? 128 : 256;
   L.nblocks = (int)((nodes + L.block - 1) / L.block);
   // population regions start on 256-byte boundaries; planes hold whole tiles
@@ -987,21 +988,31 @@ extern "C" lbm_status lbm_fields_noalloc(lbm_lattice* h, double* rho, double* ux
 extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {
   if (!h || !nu) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
   if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_nusselt is not available for enthalpy lattices");
+  // chunks per face: about 1024 wall nodes each, at most 64, into the partials
+  // buffer (which holds at least one double per 8 nodes, more than 6 x 64
+  // whenever a face has more than 1024 nodes); a compare step that follows
+  // overwrites it anyway
+  const int dims[3] = {h->p.nx, h->p.ny, h->p.nz};
+  int face_max = 1;
+  for (int a = 0; a < 3; ++a) face_max = std::max(face_max, dims[(a + 1) % 3] * dims[(a + 2) % 3]);
+  const int chunks = std::max(1, std::min(64, face_max / 1024));
   with_types(h, [&](auto lat, auto s_t, auto c_t, const auto& kp) {
     using Lat = decltype(lat);
     using S = decltype(s_t);
     using C = decltype(c_t);
     const S st_ = make_store<S>(h);
     if (h->parity)
-      hipLaunchKernelGGL((k_wall_flux<Lat, S, C, true>), dim3(6), dim3(256), 0, h->stream, kp, st_, h->dev_iso, h->res + 8);
+      hipLaunchKernelGGL((k_wall_flux<Lat, S, C, true>), dim3(chunks, 6), dim3(256), 0, h->stream, kp, st_, h->dev_iso,
+                         h->part);
     else
-      hipLaunchKernelGGL((k_wall_flux<Lat, S, C, false>), dim3(6), dim3(256), 0, h->stream, kp, st_, h->dev_iso, h->res + 8);
+      hipLaunchKernelGGL((k_wall_flux<Lat, S, C, false>), dim3(chunks, 6), dim3(256), 0, h->stream, kp, st_,
+                         h->dev_iso, h->part);
   });
+  hipLaunchKernelGGL(k_wall_fold, dim3(6), dim3(64), 0, h->stream, h->part, chunks, h->res + 8);
   lbm_status ls = launch_check("wall flux");
   if (ls != LBM_OK) return ls;
   HIP_TRY(hipMemcpyAsync(h->host_res + 8, h->res + 8, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
-  const int dims[3] = {h->p.nx, h->p.ny, h->p.nz};
   for (int f = 0; f < 6; ++f) {
     const int a = f / 2;
     const double cnt = (double)dims[(a + 1) % 3] * dims[(a + 2) % 3];

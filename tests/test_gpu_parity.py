@@ -346,6 +346,35 @@ def test_cavity256_fp32_two_steps_match_oracle():
         assert err <= 1e-5, (k, err)
 
 
+@pytest.mark.parametrize("q", [19, 15])
+def test_fp64_128_thread_blocks_match_oracle(q):
+    """FP64 flow lattices of 2^20 nodes or more step in 128-thread blocks: a
+    128x128x64 cavity (exactly 2^20 nodes) for three steps against the oracle,
+    fields to 1e-10 at both parities, and the residual r(2) of the check step
+    (snapshot at 1, compare at 2, partials folded over the 128-thread blocks)
+    against its definition applied to the oracle's fields at 1 and 2."""
+    wl = lbm_inputs.cavity((128, 128, 64), lattice=q, porosity=0.5, darcy=1e-3, rayleigh=1e5, seed=13)
+    _say(f"case fp64 128-thread blocks D3Q{q} 128x128x64 (2^20 nodes), 3 steps")
+    ref = {}
+    with oracle.Oracle(wl) as o:
+        for t in (1, 2, 3):
+            o.step(1)
+            ref[t] = o.fields()
+    a, b = ref[1], ref[2]
+    du = np.sqrt(sum(np.sum((b[k] - a[k]) ** 2) for k in ("ux", "uy", "uz")))
+    un = np.sqrt(sum(np.sum(b[k] ** 2) for k in ("ux", "uy", "uz")))
+    th_a, th_b = a["T"] + 0.5, b["T"] + 0.5
+    r_ref = max(du / un, np.sqrt(np.sum((th_b - th_a) ** 2)) / np.sqrt(np.sum(th_b ** 2)))
+    with Lattice(wl, "fp64", check_interval=2) as lat:
+        for t in (1, 2, 3):
+            lat.step(1)
+            for k, err in _field_errors(_gpu_fields(lat), ref[t]).items():
+                assert err <= 1e-10, (t, k, err)
+        r, at = lat.residual()
+    _say(f"  r(2) {r:.6e} (definition on oracle fields {r_ref:.6e})")
+    assert at == 2 and abs(r - r_ref) <= 1e-8 * r_ref, (at, r, r_ref)
+
+
 def test_largest_fp32_box_two_steps_match_oracle():
     """The largest FP32 D3Q19 box the 32-bit byte offsets allow (400x384x388,
     59.6 M nodes; its flow-population region is 4 MB short of 4 GiB): one even
