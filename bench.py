@@ -147,12 +147,12 @@ def tune_launch(workloads, precision: str, interval: int):
     return shape
 
 
-def run_solves(reqs, runs, args, budget=None, progress=_say) -> dict:
+def run_solves(reqs, runs, args, budget=None, progress=_say, sequential=True) -> dict:
     """Serves the requests once per entry of `runs` ((name, precision,
-    policy, node cap) tuples) and solves them one after another in plain FP32
-    (name "sequential_fp32"), all to residual 1e-6 with the launch shape the
-    autotuner picks for the first --tune-count workloads.  Returns name ->
-    (results, summary) and the launch shape."""
+    policy, node cap) tuples) and (unless sequential is False) solves them one
+    after another in plain FP32 (name "sequential_fp32"), all to residual 1e-6
+    with the launch shape the autotuner picks for the first --tune-count
+    workloads.  Returns name -> (results, summary) and the launch shape."""
     from paper_1611_03329_amd.serve import Server, solve_sequential, summarize
     shape = tune_launch([q.workload for q in reqs[:args.tune_count]], "fp32", 100)
     progress(f"launch shape (threads, blocks/CU, group bytes, XCD ranges) = {shape}")
@@ -165,18 +165,29 @@ def run_solves(reqs, runs, args, budget=None, progress=_say) -> dict:
         out[name] = (res, {**summarize(res), "promoted": stats["promoted"],
                            "peak_members": stats["peak_members"], "peak_bytes": stats["peak_bytes"]})
         progress(f"served {name}: {out[name][1]}")
-    seq = solve_sequential(reqs, "fp32", check_interval=100, tol=1e-6, max_steps=args.max_steps, progress=progress)
-    out["sequential_fp32"] = (seq, summarize(seq))
-    progress(f"sequential fp32: {out['sequential_fp32'][1]}")
+    if sequential:
+        seq = solve_sequential(reqs, "fp32", check_interval=100, tol=1e-6, max_steps=args.max_steps,
+                               progress=progress)
+        out["sequential_fp32"] = (seq, summarize(seq))
+        progress(f"sequential fp32: {out['sequential_fp32'][1]}")
     return out, shape
 
 
-def nu_rel_diff(res, ref) -> dict:
+def nu_rel_diff(res, ref, reqs=None, above=1e-3) -> dict:
     """Largest and median relative difference of the hot-wall Nu between two
-    runs of the same requests, over the requests both converged."""
-    d = sorted(abs(a.nu[0] - b.nu[0]) / abs(b.nu[0]) for a, b in zip(res, ref)
-               if a.converged and b.converged and a.nu and b.nu)
-    return {"max": d[-1] if d else None, "median": d[len(d) // 2] if d else None, "count": len(d)}
+    runs of the same requests, over the requests both converged; with the
+    requests given, also the ones that differ by more than `above`."""
+    pairs = [(a, b, q) for a, b, q in zip(res, ref, reqs or [None] * len(res))
+             if a.converged and b.converged and a.nu and b.nu]
+    d = sorted(abs(a.nu[0] - b.nu[0]) / abs(b.nu[0]) for a, b, _ in pairs)
+    out = {"max": d[-1] if d else None, "median": d[len(d) // 2] if d else None, "count": len(d)}
+    if reqs is not None:
+        out[f"above_{above:g}"] = [
+            {"name": a.name, "nodes": a.nodes, "steps": a.steps, "ref_steps": b.steps, "promoted_at": a.promoted_at,
+             "rayleigh": q.workload["rayleigh"], "darcy": q.workload["darcy"], "porosity": q.workload["porosity"],
+             "rel_diff": abs(a.nu[0] - b.nu[0]) / abs(b.nu[0])}
+            for a, b, q in pairs if abs(a.nu[0] - b.nu[0]) > above * abs(b.nu[0])]
+    return out
 
 
 def batched_object(args) -> dict:
@@ -231,10 +242,13 @@ def bench_solves(args, kind: str) -> int:
     nodes = sum(q.workload["nx"] * q.workload["ny"] * q.workload["nz"] for q in reqs)
     _say(f"{kind}: {len(reqs)} requests, {nodes} nodes in all; tuning the launch shape")
     cap = int(args.smallest_first_mnodes * 1e6)
-    runs, shape = run_solves(reqs, (("fp32", "fp32", "fcfs", None), ("fp16", "fp16", "fcfs", None),
-                                    ("fp32_smallest_first", "fp32", "smallest", cap)), args, budget=budget)
-    seq_res, q_sum = runs.pop("sequential_fp32")
-    main_sum = runs["fp32"][1]
+    table = {"fp32": ("fp32", "fp32", "fcfs", None), "fp16": ("fp16", "fp16", "fcfs", None),
+             "fp32_smallest_first": ("fp32_smallest_first", "fp32", "smallest", cap)}
+    names = [r for r in args.serve_runs.split(",") if r]
+    runs, shape = run_solves(reqs, [table[r] for r in names], args, budget=budget, sequential=args.sequential)
+    seq_res, q_sum = runs.pop("sequential_fp32", (None, None))
+    main = "fp32" if "fp32" in runs else names[0]
+    main_sum = runs[main][1]
     line = {
         "metric": metric,
         "value": round(main_sum["solves_per_s"], 4),
@@ -247,12 +261,16 @@ def bench_solves(args, kind: str) -> int:
         "data": "synthetic",
         "config": {"workload": workload, "requests": len(reqs), "nodes": nodes, "check_interval": 100,
                    "max_steps": args.max_steps, "launch": list(shape), "parallelism": "single GPU"},
-        "served_fp32": main_sum,
-        "served_fp16_then_fp32": runs["fp16"][1],
-        "served_fp32_smallest_first": {**runs["fp32_smallest_first"][1], "max_resident_nodes": cap},
+        "headline_run": main,
+        "served_fp32": runs["fp32"][1] if "fp32" in runs else None,
+        "served_fp16_then_fp32": runs["fp16"][1] if "fp16" in runs else None,
+        "served_fp32_smallest_first": ({**runs["fp32_smallest_first"][1], "max_resident_nodes": cap}
+                                       if "fp32_smallest_first" in runs else None),
         "sequential_fp32": q_sum,
-        "speedup_solves_per_s": {p: round(runs[p][1]["solves_per_s"] / q_sum["solves_per_s"], 3) for p in runs},
-        "nu_hot_rel_diff_vs_sequential": {p: nu_rel_diff(runs[p][0], seq_res) for p in runs},
+        "speedup_solves_per_s": (None if q_sum is None else
+                                 {p: round(runs[p][1]["solves_per_s"] / q_sum["solves_per_s"], 3) for p in runs}),
+        "nu_hot_rel_diff_vs_sequential": (None if seq_res is None else
+                                          {p: nu_rel_diff(runs[p][0], seq_res, reqs) for p in runs}),
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -491,7 +509,12 @@ def main(argv=None) -> int:
     ap.add_argument("--count", type=int, default=64, help="solves in the batched / served workloads")
     ap.add_argument("--rate", type=float, default=20.0, help="served: mean arrivals per second")
     ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="served: HBM budget for admission")
-    ap.add_argument("--max-steps", type=int, default=100_000, help="solves: step cap per solve")
+    ap.add_argument("--max-steps", type=int, default=1_000_000,
+                    help="solves: step cap per solve (a safety net: the slowest served solve takes about 5e5)")
+    ap.add_argument("--serve-runs", default="fp32,fp16,fp32_smallest_first",
+                    help="batched / served: the serving runs (fp32, fp16, fp32_smallest_first)")
+    ap.add_argument("--sequential", action=argparse.BooleanOptionalAction, default=True,
+                    help="batched / served: also solve the requests one after another in plain FP32")
     ap.add_argument("--tune-count", type=int, default=16, help="solves: workloads used to tune the launch shape")
     ap.add_argument("--smallest-first-mnodes", type=float, default=4.0,
                     help="solves: resident-node cap (millions) of the smallest-first serving run")

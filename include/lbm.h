@@ -358,8 +358,8 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_
  * replay off meanwhile): group_bytes in {0, 8, 16, 32, 64, 128, 256, 512} MiB
  * together with xcd_ranges in {0, 8}, then block in {64, 128, 256}, then
  * blocks_per_cu in {0, 4, 8}, one at a time; each candidate runs one untimed
- * and one timed interval, after the batch first steps to the start of an
- * interval.  Writes the choice to *out if non-NULL and keeps it.  The steps
+ * and three timed intervals and is scored by their median, after the batch
+ * first steps to the start of an interval.  Writes the choice to *out if non-NULL and keeps it.  The steps
  * advance the members.  Synchronizes. */
 lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out);
 

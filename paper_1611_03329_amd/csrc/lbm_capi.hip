@@ -1764,9 +1764,9 @@ extern "C" lbm_status lbm_batch_residuals(lbm_batch* b, double* r, int64_t* at_s
 // Chooses the launch shape by timing, one parameter at a time: the group size
 // limit (none, 8 MiB ... 512 MiB), the tile order (hardware order, or one
 // contiguous range per XCD), the threads per tile, then the persistent grid.
-// Each candidate runs one untimed check interval (upload, caches) and one
-// timed by HIP events; with K = 0 single steps stand in for the intervals.
-// The steps are real: the members advance.
+// Each candidate runs one untimed check interval (upload, caches) and three
+// timed by HIP events, and is scored by their median; with K = 0 single steps
+// stand in for the intervals.  The steps are real: the members advance.
 extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
   if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
   if (b->members.empty()) return fail(LBM_ERR_INVALID_ARG, "the batch is empty");
@@ -1783,16 +1783,22 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
   const bool graph = b->use_graph;
   b->use_graph = false;  // time the launches themselves
   lbm_launch cur{256, 0, 0, 0};
+  // one untimed interval (upload, caches), then the median of three timed ones
   auto trial = [&](const lbm_launch& c, float* ms) -> lbm_status {
     lbm_status s2 = lbm_batch_set_launch(b, c.block, c.blocks_per_cu, c.group_bytes, c.xcd_ranges);
     if (s2 == LBM_OK) s2 = lbm_batch_step(b, K);
     if (s2 != LBM_OK) return s2;
     if (b->dirty && (s2 = batch_upload(b)) != LBM_OK) return s2;
-    (void)hipEventRecord(e0, b->stream);
-    if ((s2 = lbm_batch_step(b, K)) != LBM_OK) return s2;
-    (void)hipEventRecord(e1, b->stream);
-    if (hipEventSynchronize(e1) != hipSuccess) return fail(LBM_ERR_DEVICE, "event synchronize failed");
-    (void)hipEventElapsedTime(ms, e0, e1);
+    float t[3];
+    for (float& ti : t) {
+      (void)hipEventRecord(e0, b->stream);
+      if ((s2 = lbm_batch_step(b, K)) != LBM_OK) return s2;
+      (void)hipEventRecord(e1, b->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) return fail(LBM_ERR_DEVICE, "event synchronize failed");
+      (void)hipEventElapsedTime(&ti, e0, e1);
+    }
+    std::sort(t, t + 3);
+    *ms = t[1];
     return LBM_OK;
   };
   const uint64_t MiB = 1ull << 20;

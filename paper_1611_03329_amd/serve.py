@@ -156,10 +156,11 @@ class Server:
     def __exit__(self, *a):
         self.close()
 
-    def run(self, requests: list, clock=time.perf_counter, progress=None) -> list:
+    def run(self, requests: list, clock=time.perf_counter, progress=None, progress_every: float = 30.0) -> list:
         """Serves `requests` (arrival times relative to the call) to completion;
         returns one Result per request, in request order.  `progress`, if
-        given, is called with a one-line status after every retirement."""
+        given, is called with a one-line status after every retirement and,
+        between retirements, at least every `progress_every` seconds."""
         first = self.precision
         pending = deque(sorted(requests, key=lambda q: q.arrival))
         need = {}
@@ -176,6 +177,7 @@ class Server:
         results = {}
         used = 0
         t0 = clock()
+        last_note = t0
 
         def next_admission():
             return pick_admission(list(waiting), need, self.policy, len(active),
@@ -224,6 +226,10 @@ class Server:
                 if len(b):
                     b.step(self.chunk)
             self.stats["chunks"] += 1
+            if progress is not None and clock() - last_note >= progress_every:
+                last_note = clock()
+                progress(f"{last_note - t0:.0f}s: {len(active)} active, {len(results)}/{len(requests)} done, "
+                         f"longest at step {max(e['base'] + e['lat'].time for e in active.values())}")
             self.stats["lattice_steps"] += self.chunk * len(active)
             self.stats["node_steps"] += self.chunk * sum(e["lat"].nodes for e in active.values())
             promote = []
@@ -302,7 +308,11 @@ def solve_sequential(requests: list, precision: str = "fp32", check_interval: in
             time.sleep(q.arrival - now)
         lat = Lattice(q.workload, precision, check_interval=K, device=device)
         res = Result(q.rid, q.workload.get("name", ""), lat.nodes, q.arrival, admitted=clock() - t0)
+        last_note = clock()
         while True:
+            if progress is not None and clock() - last_note >= 30.0:
+                last_note = clock()
+                progress(f"{last_note - t0:.0f}s: {res.name} at step {lat.time}")
             lat.step(K)
             lat.stream.synchronize()
             try:
