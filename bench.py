@@ -134,17 +134,20 @@ def _say(msg: str):
 
 def tune_launch(workloads, precision: str, interval: int):
     """Launch shape for a batch of these workloads, chosen by the batch
-    autotuner on throw-away copies (the timed solves start fresh)."""
+    autotuner on throw-away copies (the timed solves start fresh): the
+    batch-wide shape and the threads per tile of the size classes whose
+    choice differs from it."""
     from paper_1611_03329_amd import Batch, Lattice
     b = Batch(interval)
     lats = [Lattice(w, precision) for w in workloads]
     for lat in lats:
         b.add(lat)
     shape = b.autotune()
+    classes = b.class_blocks()
     b.close()
     for lat in lats:
         lat.close()
-    return shape
+    return shape, classes
 
 
 def run_solves(reqs, runs, args, budget=None, progress=_say, sequential=True) -> dict:
@@ -154,15 +157,17 @@ def run_solves(reqs, runs, args, budget=None, progress=_say, sequential=True) ->
     with the launch shape the autotuner picks for the first --tune-count
     workloads.  Returns name -> (results, summary) and the launch shape."""
     from paper_1611_03329_amd.serve import Server, solve_sequential, summarize
-    shape = tune_launch([q.workload for q in reqs[:args.tune_count]], "fp32", 100)
-    progress(f"launch shape (threads, blocks/CU, group bytes, XCD ranges) = {shape}")
+    shape, classes = tune_launch([q.workload for q in reqs[:args.tune_count]], "fp32", 100)
+    progress(f"launch shape (threads, blocks/CU, group bytes, XCD ranges) = {shape}, "
+             f"threads per tile by size class {classes}")
     out = {}
     for name, prec, policy, max_nodes in runs:
         with Server(prec, check_interval=100, tol=1e-6, max_steps=args.max_steps, hbm_budget=budget,
-                    launch=shape, policy=policy, max_nodes=max_nodes) as srv:
+                    launch=shape, policy=policy, max_nodes=max_nodes, escalate=args.escalate,
+                    class_blocks=classes) as srv:
             res = srv.run(reqs, progress=progress)
             stats = dict(srv.stats)
-        out[name] = (res, {**summarize(res), "promoted": stats["promoted"],
+        out[name] = (res, {**summarize(res), "promoted": stats["promoted"], "escalated": stats["escalated"],
                            "peak_members": stats["peak_members"], "peak_bytes": stats["peak_bytes"]})
         progress(f"served {name}: {out[name][1]}")
     if sequential:
@@ -170,7 +175,7 @@ def run_solves(reqs, runs, args, budget=None, progress=_say, sequential=True) ->
                                progress=progress)
         out["sequential_fp32"] = (seq, summarize(seq))
         progress(f"sequential fp32: {out['sequential_fp32'][1]}")
-    return out, shape
+    return out, (shape, classes)
 
 
 def nu_rel_diff(res, ref, reqs=None, above=1e-3) -> dict:
@@ -209,7 +214,8 @@ def batched_object(args) -> dict:
     return {
         "workload": f"{len(reqs)} porous cavities, edge from {{32,48,64,96,128}}, phi U[0.3,0.9], Da logU[1e-5,1e-1], "
                     "Ra logU[1e3,1e6], Pr 1, FP32, seed 4, all submitted at t=0, each to residual 1e-6",
-        "requests": len(reqs), "nodes": nodes, "max_steps": args.max_steps, "launch": list(shape),
+        "requests": len(reqs), "nodes": nodes, "max_steps": args.max_steps, "launch": list(shape[0]),
+        "class_blocks": shape[1],
         "served_fp32_smallest_first": {**served, "max_resident_nodes": cap},
         "sequential_fp32": seq,
         "speedup_solves_per_s": round(served["solves_per_s"] / seq["solves_per_s"], 4),
@@ -260,7 +266,8 @@ def bench_solves(args, kind: str) -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "requests": len(reqs), "nodes": nodes, "check_interval": 100,
-                   "max_steps": args.max_steps, "launch": list(shape), "parallelism": "single GPU"},
+                   "max_steps": args.max_steps, "launch": list(shape[0]), "class_blocks": shape[1],
+                   "parallelism": "single GPU"},
         "headline_run": main,
         "served_fp32": runs["fp32"][1] if "fp32" in runs else None,
         "served_fp16_then_fp32": runs["fp16"][1] if "fp16" in runs else None,
@@ -272,6 +279,50 @@ def bench_solves(args, kind: str) -> int:
         "nu_hot_rel_diff_vs_sequential": (None if seq_res is None else
                                           {p: nu_rel_diff(runs[p][0], seq_res, reqs) for p in runs}),
     }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_nu_steady(args) -> int:
+    """How far a solve stopped at residual 1e-6 is from the steady state: for
+    the served requests named in --requests, the hot-wall Nu of the plain FP32
+    solve, of the FP16-then-FP32 served solve and of an FP64 run continued
+    until its residual is below 1e-10 (the steady state), one JSON line."""
+    import torch
+
+    import lbm_inputs
+    from paper_1611_03329_amd import Lattice
+    from paper_1611_03329_amd.serve import Request, Server, solve_sequential
+
+    torch.cuda.set_device(0)
+    names = [n for n in args.requests.split(",") if n]
+    reqs = [wl for _, wl in lbm_inputs.config_serving(args.count, rate=args.rate) if wl["name"] in names]
+    out = {}
+    for wl in reqs:
+        q = Request(0, 0.0, wl)
+        (s32,) = solve_sequential([q], "fp32", check_interval=100, tol=1e-6, max_steps=args.max_steps)
+        with Server("fp16", check_interval=100, tol=1e-6, max_steps=args.max_steps) as srv:
+            (s16,) = srv.run([q])
+        with Lattice(wl, "fp64", check_interval=100) as lat:
+            r = 1.0
+            while r >= 1e-10 and lat.time < 2_000_000:
+                lat.step(5000)
+                r, _ = lat.residual()
+            nu_inf, t_inf = lat.nusselt()[0], lat.time
+        rec = {"nodes": wl["nx"] * wl["ny"] * wl["nz"], "rayleigh": wl["rayleigh"], "darcy": wl["darcy"],
+               "porosity": wl["porosity"], "steady_fp64": {"steps": t_inf, "residual": r, "nu": nu_inf}}
+        for key, res in (("fp32", s32), ("fp16_then_fp32", s16)):
+            rec[key] = {"steps": res.steps, "converged": res.converged, "residual": res.residual, "nu": res.nu[0],
+                        "promoted_at": res.promoted_at, "nu_rel_to_steady": abs(res.nu[0] - nu_inf) / abs(nu_inf)}
+        out[wl["name"]] = rec
+        _say(f"{wl['name']}: FP32 {rec['fp32']['nu_rel_to_steady']:.2e}, FP16 then FP32 "
+             f"{rec['fp16_then_fp32']['nu_rel_to_steady']:.2e} from the steady Nu {nu_inf:.6f}")
+    line = {"metric": "hot-wall Nu of solves stopped at residual 1e-6, against the steady state",
+            "value": max(r["fp32"]["nu_rel_to_steady"] for r in out.values()) if out else None,
+            "unit": "relative", "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "served porous-cavity requests (seed 5), residual 1e-6; steady state: FP64 "
+                                   "to residual 1e-10", "requests": names},
+            "requests": out}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -504,8 +555,12 @@ def bench_melting(args) -> int:
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("cavity256", "batched", "served", "channel", "melting", "parity32"),
-                    default="cavity256")
+    ap.add_argument("--workload", choices=("cavity256", "batched", "served", "channel", "melting", "parity32",
+                                           "nu-steady"), default="cavity256")
+    ap.add_argument("--requests", default="cavity53_phi0.533_Da6.17e-02_Ra1.33e+04,"
+                    "cavity93_phi0.490_Da3.53e-02_Ra3.16e+04,cavity126_phi0.337_Da5.33e-02_Ra2.83e+05,"
+                    "cavity48_phi0.309_Da5.32e-02_Ra4.78e+03,cavity103_phi0.781_Da1.19e-05_Ra1.60e+03",
+                    help="nu-steady: names of served requests to study")
     ap.add_argument("--count", type=int, default=64, help="solves in the batched / served workloads")
     ap.add_argument("--rate", type=float, default=20.0, help="served: mean arrivals per second")
     ap.add_argument("--hbm-budget-gib", type=float, default=16.0, help="served: HBM budget for admission")
@@ -513,6 +568,9 @@ def main(argv=None) -> int:
                     help="solves: step cap per solve (a safety net: the slowest served solve takes about 5e5)")
     ap.add_argument("--serve-runs", default="fp32,fp16,fp32_smallest_first",
                     help="batched / served: the serving runs (fp32, fp16, fp32_smallest_first)")
+    ap.add_argument("--escalate", action=argparse.BooleanOptionalAction, default=True,
+                    help="batched / served: a served solve whose FP32 residual stalls above the tolerance "
+                         "finishes in FP64 (the sequential baseline stays plain FP32)")
     ap.add_argument("--sequential", action=argparse.BooleanOptionalAction, default=True,
                     help="batched / served: also solve the requests one after another in plain FP32")
     ap.add_argument("--tune-count", type=int, default=16, help="solves: workloads used to tune the launch shape")
@@ -550,6 +608,8 @@ def main(argv=None) -> int:
         return bench_parity32(args)
     if args.workload == "channel":
         return bench_channel(args)
+    if args.workload == "nu-steady":
+        return bench_nu_steady(args)
     if args.workload != "cavity256":
         return bench_solves(args, args.workload)
 

@@ -357,11 +357,24 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_
 /* Chooses the launch shape by timing whole check intervals (HIP events, graph
  * replay off meanwhile): group_bytes in {0, 8, 16, 32, 64, 128, 256, 512} MiB
  * together with xcd_ranges in {0, 8}, then block in {64, 128, 256}, then
- * blocks_per_cu in {0, 4, 8}, one at a time; each candidate runs one untimed
- * and three timed intervals and is scored by their median, after the batch
- * first steps to the start of an interval.  Writes the choice to *out if non-NULL and keeps it.  The steps
- * advance the members.  Synchronizes. */
+ * blocks_per_cu in {0, 4, 8}, one at a time, then the threads per tile of
+ * each size class present (lbm_batch_set_class_block), one class at a time;
+ * each candidate runs one untimed and three timed intervals and is scored by
+ * their median, after the batch first steps to the start of an interval.
+ * Writes the batch-wide choice to *out if non-NULL and keeps it with the
+ * per-class ones (lbm_batch_class_block reads them).  The steps advance the
+ * members.  Synchronizes. */
 lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out);
+
+/* Threads per tile (64, 128 or 256; 0: the batch's `block` of
+ * lbm_batch_set_launch) for members of size class `size_class` in [0, 31]:
+ * those of 2^size_class to 2^(size_class + 1) - 1 nodes.  Members whose
+ * threads per tile differ launch in separate groups.  A member's state does not
+ * depend on it; its residual's summation order does. */
+lbm_status lbm_batch_set_class_block(lbm_batch* b, int32_t size_class, int32_t block);
+
+/* Threads per tile the members of size class `size_class` take. */
+lbm_status lbm_batch_class_block(const lbm_batch* b, int32_t size_class, int32_t* block);
 
 /* on != 0: the residual of a check compares with the state of K steps before
  * (r = max(|u(n) - u(n-K)|_2 / |u(n)|_2, |theta(n) - theta(n-K)|_2 /

@@ -1263,8 +1263,12 @@ struct lbm_batch {
   std::vector<int> fresh;             // a result row not yet pulled into the member
   struct Group {
     int gen, first, count, tiles;
-    int sep;  // FP16 storage with separable tiles: the odd step takes the SEP kernel
+    int sep;    // FP16 storage with separable tiles: the odd step takes the SEP kernel
+    int block;  // threads per tile of every member of the group
   };
+  // threads per tile by size class (class k: members of 2^k to 2^(k+1) - 1
+  // nodes); 0: the batch's `block`
+  int class_block[32] = {};
   std::vector<Group> groups;
   std::vector<int> slot;  // member index -> its row in the member table and in out
   void* dev_mem = nullptr;
@@ -1289,6 +1293,17 @@ static bool member_general(const lbm_lattice* h) {
 // tiles with FP16 storage (its odd step takes the SEP kernel).
 static int member_variant(const lbm_lattice* h) {
   return (member_general(h) ? 1 : 0) | (h->prec == LBM_FP16_STORAGE && h->kf.sep ? 2 : 0);
+}
+
+// Size class of member h (floor of log2 of its node count) and its threads per tile.
+static int member_class(const lbm_lattice* h) {
+  int k = 0;
+  while (k < 31 && (2ll << k) <= (long long)h->nodes) ++k;
+  return k;
+}
+static int member_block(const lbm_batch* b, const lbm_lattice* h) {
+  const int c = b->class_block[member_class(h)];
+  return c > 0 ? c : b->block;
 }
 
 // Bytes of populations a step streams for member h.
@@ -1344,17 +1359,20 @@ static lbm_status batch_upload_typed(lbm_batch* b) {
   std::vector<Member<S, C>> table;
   b->groups.clear();
   b->slot.assign(b->members.size(), 0);
-  for (int var = 0; var < 4; ++var) {
+  // members of one launch share the wall-rule variant and the threads per tile
+  const int blocks[3] = {64, 128, 256};
+  for (int vb = 0; vb < 12; ++vb) {
+    const int var = vb / 3, bl = blocks[vb % 3];
     const int gen = var & 1, sep = var >> 1;
-    lbm_batch::Group cur{gen, (int)table.size(), 0, 0, sep};
+    lbm_batch::Group cur{gen, (int)table.size(), 0, 0, sep, bl};
     uint64_t bytes = 0;
     for (size_t i = 0; i < b->members.size(); ++i) {
       lbm_lattice* h = b->members[i];
-      if (member_variant(h) != var) continue;
+      if (member_variant(h) != var || member_block(b, h) != bl) continue;
       const uint64_t mb = member_state_bytes(h);
       if (cur.count > 0 && b->group_bytes > 0 && bytes + mb > b->group_bytes) {
         b->groups.push_back(cur);
-        cur = lbm_batch::Group{gen, (int)table.size(), 0, 0, sep};
+        cur = lbm_batch::Group{gen, (int)table.size(), 0, 0, sep, bl};
         bytes = 0;
       }
       Member<S, C> m;
@@ -1366,7 +1384,7 @@ static lbm_status batch_upload_typed(lbm_batch* b) {
       m.res = h->res;
       m.clk = h->clk;
       m.block0 = cur.tiles;
-      m.nblocks = (h->nodes + b->block - 1) / b->block;
+      m.nblocks = (h->nodes + bl - 1) / bl;
       m.check = b->compare_ok[i];
       cur.tiles += m.nblocks;
       cur.count += 1;
@@ -1414,7 +1432,7 @@ static lbm_status batch_upload_typed(lbm_batch* b) {
   // valid while the buffers, the groups and the launch shape are unchanged
   std::vector<int64_t> k = {(int64_t)(uintptr_t)b->dev_mem, (int64_t)(uintptr_t)b->dev_out,
                             (int64_t)(uintptr_t)b->host_out, b->block, b->per_cu, b->check, b->nxcd};
-  for (const auto& g : b->groups) k.insert(k.end(), {g.gen, g.first, g.count, g.tiles, g.sep});
+  for (const auto& g : b->groups) k.insert(k.end(), {g.gen, g.first, g.count, g.tiles, g.sep, g.block});
   if (k != b->key) batch_drop_graphs(b);
   b->key = k;
   return LBM_OK;
@@ -1458,19 +1476,19 @@ static void batch_launch_mode(const lbm_batch* b, const lbm_batch::Group& g) {
   if constexpr (kStochastic<S> && ODD) {
     if (g.sep) {
       if (g.gen)
-        hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, true, true>()), dim3(grid), dim3(b->block), 0, b->stream,
+        hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, true, true>()), dim3(grid), dim3(g.block), 0, b->stream,
                            mem, g.count, g.tiles, b->nxcd);
       else
-        hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, false, true>()), dim3(grid), dim3(b->block), 0,
+        hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, false, true>()), dim3(grid), dim3(g.block), 0,
                            b->stream, mem, g.count, g.tiles, b->nxcd);
       return;
     }
   }
   if (g.gen)
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, true>()), dim3(grid), dim3(b->block), 0, b->stream, mem, g.count,
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, true>()), dim3(grid), dim3(g.block), 0, b->stream, mem, g.count,
                        g.tiles, b->nxcd);
   else
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, false>()), dim3(grid), dim3(b->block), 0, b->stream, mem, g.count,
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, MODE, false>()), dim3(grid), dim3(g.block), 0, b->stream, mem, g.count,
                        g.tiles, b->nxcd);
 }
 
@@ -1686,6 +1704,25 @@ extern "C" lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t 
   return LBM_OK;
 }
 
+extern "C" lbm_status lbm_batch_set_class_block(lbm_batch* b, int32_t size_class, int32_t block) {
+  if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+  if (size_class < 0 || size_class > 31) return fail(LBM_ERR_INVALID_ARG, "size class must be in [0, 31] (got %d)", size_class);
+  if (block != 0 && block != 64 && block != 128 && block != 256)
+    return fail(LBM_ERR_INVALID_ARG, "block must be 0, 64, 128 or 256 (got %d)", block);
+  if (b->class_block[size_class] != block) {
+    b->class_block[size_class] = block;
+    b->dirty = true;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_class_block(const lbm_batch* b, int32_t size_class, int32_t* block) {
+  if (!b || !block) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (size_class < 0 || size_class > 31) return fail(LBM_ERR_INVALID_ARG, "size class must be in [0, 31] (got %d)", size_class);
+  *block = b->class_block[size_class] > 0 ? b->class_block[size_class] : b->block;
+  return LBM_OK;
+}
+
 extern "C" lbm_status lbm_batch_set_span(lbm_batch* b, int32_t on) {
   if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
   if ((on != 0) == b->span) return LBM_OK;
@@ -1763,7 +1800,8 @@ extern "C" lbm_status lbm_batch_residuals(lbm_batch* b, double* r, int64_t* at_s
 
 // Chooses the launch shape by timing, one parameter at a time: the group size
 // limit (none, 8 MiB ... 512 MiB), the tile order (hardware order, or one
-// contiguous range per XCD), the threads per tile, then the persistent grid.
+// contiguous range per XCD), the threads per tile, the persistent grid, then
+// the threads per tile of each size class of members on its own.
 // Each candidate runs one untimed check interval (upload, caches) and three
 // timed by HIP events, and is scored by their median; with K = 0 single steps
 // stand in for the intervals.  The steps are real: the members advance.
@@ -1782,6 +1820,8 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
   }
   const bool graph = b->use_graph;
   b->use_graph = false;  // time the launches themselves
+  for (int& k : b->class_block) k = 0;  // the search starts from one shape for every class
+  b->dirty = true;
   lbm_launch cur{256, 0, 0, 0};
   // one untimed interval (upload, caches), then the median of three timed ones
   auto trial = [&](const lbm_launch& c, float* ms) -> lbm_status {
@@ -1833,6 +1873,23 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
     c.blocks_per_cu = pc;
     if ((st_ = trial(c, &ms)) != LBM_OK) break;
     if (ms < best) best = ms, cur.blocks_per_cu = pc;
+  }
+  // then the threads per tile of each size class present, one class at a time
+  // (members of a class whose choice differs from the rest launch apart)
+  bool present[32] = {};
+  for (const lbm_lattice* h : b->members) present[member_class(h)] = true;
+  for (int k = 0; k < 32 && st_ == LBM_OK; ++k) {
+    if (!present[k]) continue;
+    int keep = 0;
+    for (int bl : blocks_c) {
+      if (bl == cur.block) continue;
+      b->class_block[k] = bl;
+      b->dirty = true;
+      if ((st_ = trial(cur, &ms)) != LBM_OK) break;
+      if (ms < best) best = ms, keep = bl;
+    }
+    b->class_block[k] = keep;
+    b->dirty = true;
   }
   b->use_graph = graph;
   (void)hipEventDestroy(e0);

@@ -130,12 +130,14 @@ _lib.lbm_batch_set_launch.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, ctypes
 _lib.lbm_batch_autotune.argtypes = [_V, ctypes.POINTER(Launch)]
 _lib.lbm_batch_set_graph.argtypes = [_V, ctypes.c_int32]
 _lib.lbm_batch_set_span.argtypes = [_V, ctypes.c_int32]
+_lib.lbm_batch_set_class_block.argtypes = [_V, ctypes.c_int32, ctypes.c_int32]
+_lib.lbm_batch_class_block.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
 for _name in ("lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_step",
               "lbm_time", "lbm_derived_params", "lbm_fields", "lbm_fields_noalloc", "lbm_nusselt", "lbm_residual",
               "lbm_totals", "lbm_get_state", "lbm_set_state", "lbm_transfer_state", "lbm_enthalpy_fields", "lbm_batch_create", "lbm_batch_destroy",
               "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size", "lbm_batch_member", "lbm_batch_step",
               "lbm_batch_residuals", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_set_graph",
-              "lbm_batch_set_span"):
+              "lbm_batch_set_span", "lbm_batch_set_class_block", "lbm_batch_class_block"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -432,6 +434,22 @@ class Batch:
         c = Launch()
         _check(_lib.lbm_batch_autotune(self._h, ctypes.byref(c)))
         return int(c.block), int(c.blocks_per_cu), int(c.group_bytes), int(c.xcd_ranges)
+
+    def set_class_block(self, size_class: int, block: int):
+        """Threads per tile for members of 2^size_class .. 2^(size_class+1) - 1
+        nodes (0: the batch-wide block)."""
+        _check(_lib.lbm_batch_set_class_block(self._h, int(size_class), int(block)))
+
+    def class_blocks(self) -> dict:
+        """Threads per tile of every size class whose choice differs from the
+        batch-wide block, {size_class: block}."""
+        base = ctypes.c_int32()
+        out = {}
+        for k in range(32):
+            _check(_lib.lbm_batch_class_block(self._h, k, ctypes.byref(base)))
+            out[k] = int(base.value)
+        default = max(set(out.values()), key=list(out.values()).count)
+        return {k: v for k, v in out.items() if v != default}
 
     def residuals(self):
         """(r, at_step, unstable) lists in member order."""

@@ -60,6 +60,7 @@ class Result:
     unstable: bool = False
     nu: tuple = ()          # face Nusselt numbers at retirement
     promoted_at: int = -1   # steps taken in FP16 storage before the move to FP32
+    escalated_at: int = -1  # steps taken before the move from FP32 to FP64 storage
     fields: dict | None = None  # rho, ux, uy, uz, T at retirement (host arrays), if kept
 
     @property
@@ -105,13 +106,22 @@ class Server:
     the FP32 lattice starts its own check schedule at time 0, so results stay
     independent of the mix.
 
+    escalate=True: a solve whose FP32 residual stops falling above the
+    tolerance (no new low by the factor plateau_fp32[0] within plateau_fp32[1]
+    checks) moves on to FP64 storage and finishes there.  FP32 rounding puts
+    a floor under the one-step residual too, far lower than FP16's but, on
+    nearly stagnant flows (strong Darcy drag, low Ra), above 1e-6.  A solve
+    reserves at admission the bytes of the largest pair of consecutive
+    precisions it may hold at once, so its moves never wait for memory.
+
     Every batch advances `check_interval` steps per round trip; admission and
     retirement happen between these chunks."""
 
     def __init__(self, precision: str = "fp32", check_interval: int = 100, tol: float = 1e-6,
                  max_steps: int = 200_000, hbm_budget: int | None = None, max_members: int = 256,
                  graph: bool = True, launch: tuple | None = None, plateau: tuple = (0.9, 5), device=None,
-                 policy: str = "fcfs", max_nodes: int | None = None, keep_fields: bool = False):
+                 policy: str = "fcfs", max_nodes: int | None = None, keep_fields: bool = False,
+                 escalate: bool = False, plateau_fp32: tuple = (0.9, 50), class_blocks: dict | None = None):
         if check_interval <= 0 or check_interval % 2:
             raise ValueError("check_interval must be a positive even number (chunks keep the parity)")
         if precision not in ("fp32", "fp16"):
@@ -130,6 +140,10 @@ class Server:
         self.tol = float(tol)
         self.max_steps = int(max_steps)
         self.plateau = (float(plateau[0]), int(plateau[1]))
+        # the precisions a solve goes through, and the plateau rule that moves
+        # it on from each but the last
+        self.ladder = (["fp16"] if precision == "fp16" else []) + ["fp32"] + (["fp64"] if escalate else [])
+        self.plateaus = {"fp16": self.plateau, "fp32": (float(plateau_fp32[0]), int(plateau_fp32[1]))}
         self.device = torch.device("cuda") if device is None else torch.device(device)
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info(self.device)
@@ -137,14 +151,16 @@ class Server:
         self.hbm_budget = int(hbm_budget)
         self.max_members = int(max_members)
         # one batch per storage precision, each on a stream of its own
-        self.batches = {"fp32": Batch(self.K, graph=graph, device=self.device)}
-        if precision == "fp16":
-            self.batches["fp16"] = Batch(self.K, graph=graph, device=self.device)
+        self.batches = {p: Batch(self.K, graph=graph, device=self.device) for p in self.ladder}
         if launch is not None:
             for b in self.batches.values():
                 b.set_launch(*launch)
+        # threads per tile by member size class, e.g. as the autotuner chose them
+        for k, blk in (class_blocks or {}).items():
+            for b in self.batches.values():
+                b.set_class_block(k, blk)
         self.stats = {"chunks": 0, "lattice_steps": 0, "node_steps": 0, "peak_members": 0, "peak_bytes": 0,
-                      "promoted": 0}
+                      "promoted": 0, "escalated": 0}
 
     def close(self):
         for b in self.batches.values():
@@ -161,14 +177,17 @@ class Server:
         returns one Result per request, in request order.  `progress`, if
         given, is called with a one-line status after every retirement and,
         between retirements, at least every `progress_every` seconds."""
-        first = self.precision
+        ladder = self.ladder
+        first = ladder[0]
         pending = deque(sorted(requests, key=lambda q: q.arrival))
         need = {}
+
+        def reserve(rid, level):
+            return reserve_bytes([need[rid][p] for p in ladder], level)
+
         for q in requests:
-            need[q.rid] = {p: required_bytes(make_params(q.workload, p, self.K)) for p in self.batches}
-            # an FP16 solve reserves room for its FP32 copy as well, so that its
-            # move can never wait for memory
-            need[q.rid]["admit"] = sum(need[q.rid].values()) if first == "fp16" else need[q.rid]["fp32"]
+            need[q.rid] = {p: required_bytes(make_params(q.workload, p, self.K)) for p in ladder}
+            need[q.rid]["admit"] = reserve(q.rid, 0)
             need[q.rid]["nodes"] = q.workload["nx"] * q.workload["ny"] * q.workload["nz"]
             if need[q.rid]["admit"] > self.hbm_budget:
                 raise ValueError(f"request {q.rid} needs more than the HBM budget")
@@ -214,7 +233,7 @@ class Server:
                 self.batches[first].add(lat)
                 res = Result(q.rid, q.workload.get("name", ""), lat.nodes, q.arrival, admitted=clock() - t0)
                 active[id(lat)] = {"lat": lat, "res": res, "bytes": need[q.rid]["admit"], "q": q, "prec": first,
-                                   "base": 0, "best": math.inf, "since": 0}
+                                   "level": 0, "base": 0, "best": math.inf, "since": 0}
                 used += need[q.rid]["admit"]
             self.stats["peak_members"] = max(self.stats["peak_members"], len(active))
             self.stats["peak_bytes"] = max(self.stats["peak_bytes"], used)
@@ -244,31 +263,46 @@ class Server:
                     if _done(res, rr, aa, uu, steps, self.tol, self.max_steps):
                         b.remove(lat)
                         retire(lat, e)
-                    elif prec == "fp16" and aa > 0:
-                        # the FP16 floor: no new low by the factor within the last checks
-                        if rr < e["best"] * self.plateau[0]:
+                    elif e["level"] + 1 < len(ladder) and aa > 0:
+                        # the precision's floor: no new low by the factor within the last checks
+                        factor, checks = self.plateaus[prec]
+                        if rr < e["best"] * factor:
                             e["best"], e["since"] = rr, 0
                         else:
                             e["since"] += 1
-                        if e["since"] >= self.plateau[1]:
+                        if e["since"] >= checks:
                             promote.append(lat)
             for lat in promote:
                 e = active[id(lat)]
-                n32 = need[e["q"].rid]["fp32"]
-                new = Lattice(e["q"].workload, "fp32", device=self.device)
+                level = e["level"] + 1
+                nxt = ladder[level]
+                new = Lattice(e["q"].workload, nxt, device=self.device)
                 new.transfer_from(lat)
-                self.batches["fp16"].remove(lat)
-                e["res"].promoted_at = e["base"] + lat.time
+                self.batches[e["prec"]].remove(lat)
+                if e["prec"] == "fp16":
+                    e["res"].promoted_at = e["base"] + lat.time
+                    self.stats["promoted"] += 1
+                else:
+                    e["res"].escalated_at = e["base"] + lat.time
+                    self.stats["escalated"] += 1
                 e["base"] += lat.time
                 lat.close()
                 del active[id(lat)]
-                self.batches["fp32"].add(new)
-                # the FP16 lattice's share of the reservation is free again
-                used -= e["bytes"] - n32
-                e.update(lat=new, bytes=n32, prec="fp32")
+                self.batches[nxt].add(new)
+                # the reservation shrinks to what the remaining moves need
+                nb = reserve(e["q"].rid, level)
+                used -= e["bytes"] - nb
+                e.update(lat=new, bytes=nb, prec=nxt, level=level, best=math.inf, since=0)
                 active[id(new)] = e
-                self.stats["promoted"] += 1
         return [results[q.rid] for q in requests]
+
+
+def reserve_bytes(sizes: list, level: int) -> int:
+    """Device bytes a solve reserves at ladder level `level`, given its
+    lattice's bytes at each precision of the ladder: the largest pair of
+    consecutive precisions it may still hold at once (a move copies the old
+    state into the new lattice before the old one is freed)."""
+    return max(sizes[j] + (sizes[j + 1] if j + 1 < len(sizes) else 0) for j in range(level, len(sizes)))
 
 
 def pick_admission(waiting: list, need: dict, policy: str, n_active: int, resident_nodes: int, used: int,

@@ -262,6 +262,34 @@ def test_graph_replay_matches_eager(group):
             x.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_size_class_tiles_keep_results(prec):
+    """Members of different size classes on different tile sizes (64 threads
+    for the smallest classes, 128 for the middle ones, the batch's 256 for the
+    rest) launch in separate groups and still equal their solo states bit for
+    bit, at both parities."""
+    _say(f"case size-class tiles {prec}")
+    ms = _members()
+    solo = {k: _make(wl, sd, prec, 0) for k, (wl, sd) in ms.items()}
+    with Batch(check_interval=6) as b:
+        for k_, blk in ((8, 64), (9, 64), (10, 128), (12, 128)):
+            b.set_class_block(k_, blk)
+        mem = {k: _make(wl, sd, prec, 0) for k, (wl, sd) in ms.items()}
+        for k in ms:
+            b.add(mem[k])
+        assert b.class_blocks() == {8: 64, 9: 64, 10: 128, 12: 128}
+        for n in (1, 4, 13):
+            b.step(n)
+            for k in ms:
+                solo[k].step(n)
+            for k in ms:
+                assert _same(mem[k], solo[k]), (k, solo[k].time)
+        for m in list(mem.values()):
+            m.close()
+    for x in solo.values():
+        x.close()
+
+
 def test_autotune_keeps_results():
     """The autotuner picks one of the admissible launch shapes; the steps it
     takes are ordinary steps (the state still equals the solo state)."""
@@ -274,9 +302,14 @@ def test_autotune_keeps_results():
         block, per_cu, group, xcd = b.autotune()
         assert block in (64, 128, 256) and per_cu in (0, 4, 8) and xcd in (0, 8)
         assert group in [0] + [m * MiB for m in (8, 16, 32, 64, 128, 256, 512)]
+        classes = {int(np.floor(np.log2(m.nodes))) for m in mem.values()}
+        tuned = b.class_blocks()
+        assert set(tuned) <= classes and set(tuned.values()) <= {64, 128, 256}
         b.step(4)
         steps = mem["cavity"].time
-        assert steps == 20 * 2 * 10 + 4   # 16 group/order pairs + 2 tile sizes + 2 grids, two intervals each
+        # 16 group/order pairs + 2 tile sizes + 2 grids + 2 tile sizes per size
+        # class, four intervals each (one untimed, three timed)
+        assert steps == (16 + 2 + 2 + 2 * len(classes)) * 4 * 10 + 4
         for k, (w, s) in ms.items():
             ref = _make(w, s, "fp32", 0)
             ref.step(steps)

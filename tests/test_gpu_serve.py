@@ -81,6 +81,32 @@ def test_served_solves_match_the_oracle(prec):
         assert max(e_nu) <= bound_nu, (q.rid, e_nu)
 
 
+def test_escalation_to_fp64_below_the_fp32_floor():
+    """A tolerance below what FP32 storage can reach (1e-10): with escalation
+    the server moves each solve to FP64 once its FP32 residual stalls, and the
+    solve converges; its Nu then matches the FP64 oracle stepped as many steps
+    (the FP32 phase's rounding relaxed away), and each result is the same
+    alone and in the mix."""
+    reqs = [_requests()[i] for i in (0, 2)]
+    kw = dict(check_interval=100, tol=1e-10, max_steps=80000, escalate=True, plateau_fp32=(0.9, 5))
+    _say("case escalation fp32 -> fp64, tol 1e-10")
+    with Server("fp32", **kw) as srv:
+        mix = srv.run(reqs)
+        assert srv.stats["escalated"] == len(reqs)
+    for q, m in zip(reqs, mix):
+        assert m.converged and m.escalated_at > 0, (q.rid, m.residual, m.steps, m.escalated_at)
+        with oracle.Oracle(q.workload) as o:
+            o.step(m.steps)
+            nu_ref = o.nusselt()
+        e_nu = abs(m.nu[0] - nu_ref[0]) / abs(nu_ref[0])
+        _say(f"{q.workload['name']}: steps {m.steps}, fp64 from {m.escalated_at}, Nu rel {e_nu:.2e}")
+        assert e_nu <= 1e-8, e_nu
+        with Server("fp32", **kw) as srv1:
+            (a,) = srv1.run([Request(q.rid, 0.0, q.workload)])
+        assert ((a.steps, a.checked_at, a.residual, a.nu, a.escalated_at)
+                == (m.steps, m.checked_at, m.residual, m.nu, m.escalated_at)), q.rid
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
 def test_results_are_the_same_alone_and_in_the_mix(prec):
     reqs = _requests()

@@ -50,6 +50,19 @@ def test_capped_solves_are_not_counted_as_solves():
     assert abs(s["mlups"] - 4 * 1000 * 100 / 4.0 / 1e6) < 1e-12
 
 
+def test_reservations_cover_every_move():
+    """A solve reserves, at each ladder level, the largest sum of two
+    consecutive precisions it may still hold at once; the reservation never
+    grows as it moves on."""
+    from paper_1611_03329_amd.serve import reserve_bytes
+    b16, b32, b64 = 136, 208, 416
+    assert reserve_bytes([b32], 0) == b32
+    assert reserve_bytes([b16, b32], 0) == b16 + b32 and reserve_bytes([b16, b32], 1) == b32
+    ladder = [b16, b32, b64]
+    assert [reserve_bytes(ladder, k) for k in range(3)] == [b32 + b64, b32 + b64, b64]
+    assert reserve_bytes([b32, b64], 0) == b32 + b64 and reserve_bytes([b32, b64], 1) == b64
+
+
 def test_admission_policies():
     """First come first served admits only the head of the queue; smallest
     first takes the fitting request with the fewest nodes; a node cap holds
