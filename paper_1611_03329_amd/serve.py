@@ -108,7 +108,9 @@ class Server:
 
     escalate=True: a solve whose FP32 residual stops falling above the
     tolerance (no new low by the factor plateau_fp32[0] within plateau_fp32[1]
-    checks) moves on to FP64 storage and finishes there.  FP32 rounding puts
+    checks: by default 1 % in 100 checks, which a decaying residual misses
+    only when its slowest mode decays over more than 10^6 steps) moves on to
+    FP64 storage and finishes there.  FP32 rounding puts
     a floor under the one-step residual too, far lower than FP16's but, on
     nearly stagnant flows (strong Darcy drag, low Ra), above 1e-6.  A solve
     reserves at admission the bytes of the largest pair of consecutive
@@ -121,7 +123,7 @@ class Server:
                  max_steps: int = 200_000, hbm_budget: int | None = None, max_members: int = 256,
                  graph: bool = True, launch: tuple | None = None, plateau: tuple = (0.9, 5), device=None,
                  policy: str = "fcfs", max_nodes: int | None = None, keep_fields: bool = False,
-                 escalate: bool = False, plateau_fp32: tuple = (0.9, 50), class_blocks: dict | None = None):
+                 escalate: bool = False, plateau_fp32: tuple = (0.99, 100), class_blocks: dict | None = None):
         if check_interval <= 0 or check_interval % 2:
             raise ValueError("check_interval must be a positive even number (chunks keep the parity)")
         if precision not in ("fp32", "fp16"):
