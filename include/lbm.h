@@ -192,7 +192,12 @@ lbm_status lbm_set_stream(lbm_lattice* h, void* stream);
  * K > 0 the steps that start at times n-1 and n (n a positive multiple of K)
  * also compute the residual r(n) (see lbm_residual).  Asynchronous; returns
  * LBM_ERR_UNSTABLE without enqueueing if an earlier check already found the
- * lattice unstable. */
+ * lattice unstable.  That test reads the host copy of the last check's result
+ * without waiting for it: a check whose copy is still in flight is seen by the
+ * first call after it has landed (at the latest after the next synchronizing
+ * call, e.g. lbm_residual), so stepping may continue up to one more call past
+ * an unstable check; the values are then meaningless but nothing else is
+ * affected. */
 lbm_status lbm_step(lbm_lattice* h, int64_t nsteps);
 
 /* Current time t (completed steps).  Host-only, no synchronization. */
