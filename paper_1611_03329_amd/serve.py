@@ -106,11 +106,13 @@ class Server:
     the FP32 lattice starts its own check schedule at time 0, so results stay
     independent of the mix.
 
-    escalate=True: a solve whose FP32 residual stops falling above the
+    escalate=True: a solve whose FP32 residual stops falling just above the
     tolerance (no new low by the factor plateau_fp32[0] within plateau_fp32[1]
-    checks: by default 1 % in 100 checks, which a decaying residual misses
-    only when its slowest mode decays over more than 10^6 steps) moves on to
-    FP64 storage and finishes there.  FP32 rounding puts
+    checks while its lowest residual is below plateau_fp32[2] times the
+    tolerance: by default 1 % in 100 checks within 10x the tolerance) moves on
+    to FP64 storage and finishes there.  The level condition keeps transient
+    bumps of the residual, far above the tolerance, from moving solves that
+    FP32 finishes by itself.  FP32 rounding puts
     a floor under the one-step residual too, far lower than FP16's but, on
     nearly stagnant flows (strong Darcy drag, low Ra), above 1e-6.  A solve
     reserves at admission the bytes of the largest pair of consecutive
@@ -123,7 +125,7 @@ class Server:
                  max_steps: int = 200_000, hbm_budget: int | None = None, max_members: int = 256,
                  graph: bool = True, launch: tuple | None = None, plateau: tuple = (0.9, 5), device=None,
                  policy: str = "fcfs", max_nodes: int | None = None, keep_fields: bool = False,
-                 escalate: bool = False, plateau_fp32: tuple = (0.99, 100), class_blocks: dict | None = None):
+                 escalate: bool = False, plateau_fp32: tuple = (0.99, 100, 10.0), class_blocks: dict | None = None):
         if check_interval <= 0 or check_interval % 2:
             raise ValueError("check_interval must be a positive even number (chunks keep the parity)")
         if precision not in ("fp32", "fp16"):
@@ -145,7 +147,11 @@ class Server:
         # the precisions a solve goes through, and the plateau rule that moves
         # it on from each but the last
         self.ladder = (["fp16"] if precision == "fp16" else []) + ["fp32"] + (["fp64"] if escalate else [])
-        self.plateaus = {"fp16": self.plateau, "fp32": (float(plateau_fp32[0]), int(plateau_fp32[1]))}
+        # (factor, checks, level): move on after `checks` checks without a new
+        # low by `factor`, once the lowest residual is below level x tol
+        self.plateaus = {"fp16": (self.plateau[0], self.plateau[1], math.inf),
+                         "fp32": (float(plateau_fp32[0]), int(plateau_fp32[1]),
+                                  float(plateau_fp32[2]) if len(plateau_fp32) > 2 else math.inf)}
         self.device = torch.device("cuda") if device is None else torch.device(device)
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info(self.device)
@@ -267,12 +273,12 @@ class Server:
                         retire(lat, e)
                     elif e["level"] + 1 < len(ladder) and aa > 0:
                         # the precision's floor: no new low by the factor within the last checks
-                        factor, checks = self.plateaus[prec]
+                        factor, checks, level = self.plateaus[prec]
                         if rr < e["best"] * factor:
                             e["best"], e["since"] = rr, 0
                         else:
                             e["since"] += 1
-                        if e["since"] >= checks:
+                        if e["since"] >= checks and e["best"] < level * self.tol:
                             promote.append(lat)
             for lat in promote:
                 e = active[id(lat)]
