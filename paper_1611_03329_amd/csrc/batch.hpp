@@ -100,11 +100,11 @@ __device__ __forceinline__ void step_tiles(const Member<S, C>* __restrict__ mem,
 }
 
 // SEP (separable tiles: the link indices of the odd step from per-axis deltas)
-// is compiled for FP16 storage only, whose step is limited by instruction
-// issue: there it saves 6-7 % of the odd step's vector instructions.  FP32
-// storage is HBM-bound, and the registers the deltas occupy made its step
-// slower.  It is a kernel of its own, not a branch: both address paths in one
-// kernel exceed the register budget below.
+// is compiled for FP16 storage only: there it takes 6-7 % of the odd step's
+// vector instructions away and 7 % of its time.  With FP32 storage the
+// registers the deltas occupy made the step slower.  It is a kernel of its
+// own, not a branch: both address paths in one kernel exceed the register
+// budget below.
 //
 // The step kernel with FP32 arithmetic (FP32 and FP16 storage) is held to 128
 // registers, 4 wavefronts per SIMD: the general wall rules alone would need up

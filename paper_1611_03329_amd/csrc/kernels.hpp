@@ -597,7 +597,7 @@ __device__ __forceinline__ void step_node(const KParams<C>& kp, const S& state, 
   C h[Lat::Q], p[7];
   // A wavefront that is issuing its loads goes before wavefronts that are
   // computing, so the loads of the next wavefronts are in flight sooner.
-  // Measured: FP16 storage (issue-bound) 3-4 % faster; FP64 (2-3 wavefronts
+  // Measured: FP16 storage 3-4 % faster; FP64 (2-3 wavefronts
   // per SIMD) 0.8-0.9 % faster; FP32 storage 0.7-0.9 % faster in the even
   // step but 1.5 % slower in the odd step, whose loads reach neighbour tiles.
   constexpr bool kLoadPriority =
