@@ -235,8 +235,18 @@ lbm_status lbm_fields_noalloc(lbm_lattice* h, double* rho, double* ux, double* u
  * sigma T_w in the lattice's arithmetic precision, as the step applies it),
  * times L/(alpha_e delta_T): the midpoint rule for Nu_3D of Eqs. 53-55.  0 for
  * other faces.  The hot wall of a cavity reports +Nu, the cold wall -Nu.
- * Synchronizes. */
+ * Synchronizes.  After lbm_nusselt_start it collects the reduction that call
+ * started instead of starting one. */
 lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]);
+
+/* Starts the reduction of lbm_nusselt on the lattice's stream for the state at
+ * the current time and returns without waiting; the next lbm_nusselt on the
+ * lattice collects it (Eqs. 53-55, as lbm_nusselt), whatever was enqueued on
+ * the stream in between.  Lets a caller that retires several lattices sharing
+ * a stream start all their reductions and synchronize once.  A second start
+ * before the collection replaces the first.  LBM_ERR_UNSUPPORTED for an
+ * enthalpy lattice. */
+lbm_status lbm_nusselt_start(lbm_lattice* h);
 
 /* Most recent residual check: r(n) = max(|u(n) - u(n-1)|_2 / |u(n)|_2,
  * |theta(n) - theta(n-1)|_2 / |theta(n)|_2), theta = (T - T_ref)/delta_T + 1/2,

@@ -74,6 +74,7 @@ struct lbm_lattice {
   int* dev_iso = nullptr;   // [6] isothermal flags
   double* host_res = nullptr; // pinned mirror of res (32 doubles)
   int parity = 0;
+  bool nu_pending = false;  // lbm_nusselt_start enqueued a wall-flux reduction not yet collected
   int64_t t = 0;
   bool snapshot_valid = false;
   int64_t snapshot_at = -1;
@@ -985,9 +986,9 @@ extern "C" lbm_status lbm_fields_noalloc(lbm_lattice* h, double* rho, double* ux
   return LBM_OK;
 }
 
-extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {
-  if (!h || !nu) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
-  if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_nusselt is not available for enthalpy lattices");
+// Enqueues the wall-flux reduction of the current state on the lattice's
+// stream and the copy of its six face sums into host_res[8..13].
+static lbm_status nusselt_enqueue(lbm_lattice* h) {
   // chunks per face: about 1024 wall nodes each, at most 64, into the partials
   // buffer (which holds at least one double per 8 nodes, more than 6 x 64
   // whenever a face has more than 1024 nodes); a compare step that follows
@@ -1012,7 +1013,27 @@ extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {
   lbm_status ls = launch_check("wall flux");
   if (ls != LBM_OK) return ls;
   HIP_TRY(hipMemcpyAsync(h->host_res + 8, h->res + 8, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_nusselt_start(lbm_lattice* h) {
+  if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
+  if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_nusselt_start is not available for enthalpy lattices");
+  const lbm_status st = nusselt_enqueue(h);
+  h->nu_pending = st == LBM_OK;
+  return st;
+}
+
+extern "C" lbm_status lbm_nusselt(lbm_lattice* h, double nu[6]) {
+  if (!h || !nu) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (h->energy) return fail(LBM_ERR_UNSUPPORTED, "lbm_nusselt is not available for enthalpy lattices");
+  if (!h->nu_pending) {
+    const lbm_status st = nusselt_enqueue(h);
+    if (st != LBM_OK) return st;
+  }
+  h->nu_pending = false;
   HIP_TRY(hipStreamSynchronize(h->stream));
+  const int dims[3] = {h->p.nx, h->p.ny, h->p.nz};
   for (int f = 0; f < 6; ++f) {
     const int a = f / 2;
     const double cnt = (double)dims[(a + 1) % 3] * dims[(a + 2) % 3];

@@ -109,6 +109,7 @@ _lib.lbm_fields.argtypes = [_V, _V, _V, _V, _V, _V]
 _lib.lbm_fields_noalloc.argtypes = [_V, _V, _V, _V, _V, _V]
 _lib.lbm_enthalpy_fields.argtypes = [_V, _V, _V, _V]
 _lib.lbm_nusselt.argtypes = [_V, _D]
+_lib.lbm_nusselt_start.argtypes = [_V]
 _lib.lbm_residual.argtypes = [_V, _D, _I64]
 _lib.lbm_totals.argtypes = [_V, _D, _D]
 _lib.lbm_get_state.argtypes = [_V, _V, _V]
@@ -133,7 +134,7 @@ _lib.lbm_batch_set_span.argtypes = [_V, ctypes.c_int32]
 _lib.lbm_batch_set_class_block.argtypes = [_V, ctypes.c_int32, ctypes.c_int32]
 _lib.lbm_batch_class_block.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
 for _name in ("lbm_required_bytes", "lbm_create", "lbm_destroy", "lbm_set_stream", "lbm_step",
-              "lbm_time", "lbm_derived_params", "lbm_fields", "lbm_fields_noalloc", "lbm_nusselt", "lbm_residual",
+              "lbm_time", "lbm_derived_params", "lbm_fields", "lbm_fields_noalloc", "lbm_nusselt", "lbm_nusselt_start", "lbm_residual",
               "lbm_totals", "lbm_get_state", "lbm_set_state", "lbm_transfer_state", "lbm_enthalpy_fields", "lbm_batch_create", "lbm_batch_destroy",
               "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size", "lbm_batch_member", "lbm_batch_step",
               "lbm_batch_residuals", "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_set_graph",
@@ -290,6 +291,11 @@ class Lattice:
         nu = (ctypes.c_double * 6)()
         _check(_lib.lbm_nusselt(self._h, nu))
         return [float(v) for v in nu]
+
+    def nusselt_start(self):
+        """Starts the Nusselt reduction of the current state without waiting;
+        the next nusselt() collects it."""
+        _check(_lib.lbm_nusselt_start(self._h))
 
     def residual(self):
         r = ctypes.c_double()

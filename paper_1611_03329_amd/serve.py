@@ -259,7 +259,7 @@ class Server:
                          f"longest at step {max(e['base'] + e['lat'].time for e in active.values())}")
             self.stats["lattice_steps"] += self.chunk * len(active)
             self.stats["node_steps"] += self.chunk * sum(e["lat"].nodes for e in active.values())
-            promote = []
+            promote, done = [], []
             for prec, b in self.batches.items():
                 if not len(b):
                     continue
@@ -270,7 +270,7 @@ class Server:
                     steps = e["base"] + lat.time
                     if _done(res, rr, aa, uu, steps, self.tol, self.max_steps):
                         b.remove(lat)
-                        retire(lat, e)
+                        done.append((lat, e))
                     elif e["level"] + 1 < len(ladder) and aa > 0:
                         # the precision's floor: no new low by the factor within the last checks
                         factor, checks, level = self.plateaus[prec]
@@ -280,6 +280,13 @@ class Server:
                             e["since"] += 1
                         if e["since"] >= checks and e["best"] < level * self.tol:
                             promote.append(lat)
+            # the retiring solves' Nusselt reductions start together; the first
+            # collection waits for all of them
+            for lat, e in done:
+                if not e["res"].unstable:
+                    lat.nusselt_start()
+            for lat, e in done:
+                retire(lat, e)
             for lat in promote:
                 e = active[id(lat)]
                 level = e["level"] + 1

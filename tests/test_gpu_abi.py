@@ -105,3 +105,21 @@ def test_create_refuses_host_memory_as_the_state_buffer():
     with Lattice(wl, "fp32") as lat:
         lat.step(2)
         assert lat.time == 2
+
+
+def test_nusselt_start_collects_the_state_it_started_on():
+    """lbm_nusselt_start enqueues the reduction of the current state; the next
+    lbm_nusselt collects it even when steps were enqueued in between, and the
+    call after that reduces the state of its own time."""
+    wl = lbm_inputs.cavity((20, 16, 12), porosity=0.5, darcy=1e-2, rayleigh=5e3, seed=23)
+    print("case nusselt_start fp32 20x16x12", flush=True)
+    with Lattice(wl, "fp32") as lat:
+        lat.step(40)
+        ref = lat.nusselt()
+        lat.nusselt_start()
+        lat.step(7)
+        assert lat.nusselt() == ref
+        now = lat.nusselt()
+        assert now != ref and now[0] != 0.0
+        lat.nusselt_start()
+        assert lat.nusselt() == now

@@ -539,7 +539,7 @@ def channel_reference():
     wl = lbm_inputs.config_channel(downscale=True)
     out = {}
     with oracle.Oracle(wl) as o:
-        for t in (200, 500):
+        for t in (200, 500, 1000):
             o.step(t - o.time)
             out[t] = {"fields": o.fields(), "nu": o.nusselt()}
     return wl, out
@@ -562,22 +562,26 @@ def test_channel_downscale_fp64_matches_oracle(channel_reference):
 @pytest.mark.parametrize("prec,tol_field,tol_nu", [("fp32", 1e-5, 1e-5), ("fp16", 1e-2, 1e-3)])
 def test_channel_downscale_reduced_precision(channel_reference, prec, tol_field, tol_nu):
     """FP32 and FP16 storage (FP32 arithmetic) against the FP64 oracle on the
-    channel downscale after 500 steps: relative global errors (Eq. 52) of u and
-    T, and the relative error of the bottom-wall Nusselt number."""
+    channel downscale after 500 and 1000 steps: relative global errors (Eq. 52)
+    of u and T, and the relative error of the bottom-wall Nusselt number.  The
+    channel heated from below with a throughflow is unstable: rounding
+    differences grow with time (FP32 E(u) 7.7e-7 at 1000 steps, 8.8e-6 at
+    2000), so the comparison stops at 1000."""
     wl, ref = channel_reference
-    _say(f"case channel 128x32x32 {prec}")
+    _say(f"case channel 128x32x32 {prec}, t = 500 and 1000")
     with Lattice(wl, prec) as lat:
-        lat.step(500)
-        fl = _gpu_fields(lat)
-        nu = lat.nusselt()
-    r = ref[500]["fields"]
-    u_g = np.stack([fl["ux"], fl["uy"], fl["uz"]])
-    u_r = np.stack([r["ux"], r["uy"], r["uz"]])
-    e_u = _global_rel(u_g, u_r)
-    e_T = _global_rel(fl["T"], r["T"])
-    e_nu = abs(nu[2] - ref[500]["nu"][2]) / abs(ref[500]["nu"][2])
-    _say(f"channel {prec}: E(u) {e_u:.3e} E(T) {e_T:.3e} Nu rel {e_nu:.3e}")
-    assert e_u <= tol_field and e_T <= tol_field and e_nu <= tol_nu
+        for t in (500, 1000):
+            lat.step(t - lat.time)
+            fl = _gpu_fields(lat)
+            nu = lat.nusselt()
+            r = ref[t]["fields"]
+            u_g = np.stack([fl["ux"], fl["uy"], fl["uz"]])
+            u_r = np.stack([r["ux"], r["uy"], r["uz"]])
+            e_u = _global_rel(u_g, u_r)
+            e_T = _global_rel(fl["T"], r["T"])
+            e_nu = abs(nu[2] - ref[t]["nu"][2]) / abs(ref[t]["nu"][2])
+            _say(f"channel {prec} t={t}: E(u) {e_u:.3e} E(T) {e_T:.3e} Nu rel {e_nu:.3e}")
+            assert e_u <= tol_field and e_T <= tol_field and e_nu <= tol_nu, t
 
 
 def test_cavity32_fp16_storage(cavity32_reference):
