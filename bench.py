@@ -261,7 +261,8 @@ def bench_solves(args, kind: str) -> int:
     _say(f"{kind}: {len(reqs)} requests, {nodes} nodes in all; tuning the launch shape")
     cap = int(args.smallest_first_mnodes * 1e6)
     table = {"fp32": ("fp32", "fp32", "fcfs", None), "fp16": ("fp16", "fp16", "fcfs", None),
-             "fp32_smallest_first": ("fp32_smallest_first", "fp32", "smallest", cap)}
+             "fp32_smallest_first": ("fp32_smallest_first", "fp32", "smallest", cap),
+             "fp16_smallest_first": ("fp16_smallest_first", "fp16", "smallest", cap)}
     names = [r for r in args.serve_runs.split(",") if r]
     runs, shape = run_solves(reqs, [table[r] for r in names], args, budget=budget, sequential=args.sequential)
     seq_res, q_sum = runs.pop("sequential_fp32", (None, None))
@@ -285,6 +286,8 @@ def bench_solves(args, kind: str) -> int:
         "served_fp16_then_fp32": runs["fp16"][1] if "fp16" in runs else None,
         "served_fp32_smallest_first": ({**runs["fp32_smallest_first"][1], "max_resident_nodes": cap}
                                        if "fp32_smallest_first" in runs else None),
+        "served_fp16_then_fp32_smallest_first": ({**runs["fp16_smallest_first"][1], "max_resident_nodes": cap}
+                                                 if "fp16_smallest_first" in runs else None),
         "sequential_fp32": q_sum,
         "speedup_solves_per_s": (None if q_sum is None else
                                  {p: round(runs[p][1]["solves_per_s"] / q_sum["solves_per_s"], 3) for p in runs}),
@@ -579,7 +582,7 @@ def main(argv=None) -> int:
     ap.add_argument("--max-steps", type=int, default=1_000_000,
                     help="solves: step cap per solve (a safety net: the slowest served solve takes about 5e5)")
     ap.add_argument("--serve-runs", default="fp32,fp16,fp32_smallest_first",
-                    help="batched / served: the serving runs (fp32, fp16, fp32_smallest_first)")
+                    help="batched / served: the serving runs (fp32, fp16, fp32_smallest_first, fp16_smallest_first)")
     ap.add_argument("--escalate", action=argparse.BooleanOptionalAction, default=True,
                     help="batched / served: a served solve whose FP32 residual stalls above the tolerance "
                          "finishes in FP64 (the sequential baseline stays plain FP32)")
