@@ -375,7 +375,9 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t block, int32_t blocks_per_
  * blocks_per_cu in {0, 4, 8}, one at a time, then the threads per tile of
  * each size class present (lbm_batch_set_class_block), one class at a time;
  * each candidate runs one untimed and three timed intervals and is scored by
- * their median, after the batch first steps to the start of an interval.
+ * their median, and replaces the incumbent only when its median is more than
+ * 1 % lower (choices inside the timing noise keep the earlier shape); the
+ * batch first steps to the start of an interval.
  * Writes the batch-wide choice to *out if non-NULL and keeps it with the
  * per-class ones (lbm_batch_class_block reads them).  The steps advance the
  * members.  Synchronizes. */

@@ -1868,6 +1868,11 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
   const int blocks_c[] = {64, 128, 256};
   const int per_cu_c[] = {0, 4, 8};
   float best = -1.0f, ms = 0.0f;
+  // a candidate replaces the incumbent only when it is faster by more than
+  // the margin: a choice inside the timing noise keeps the earlier (simpler)
+  // shape, so repeated tunings of one batch agree
+  constexpr float kMargin = 0.01f;
+  auto better = [&](float t) { return t < best * (1.0f - kMargin); };
   // group size and tile order together: which order is faster depends on
   // how much of a group the last-level cache holds
   for (uint64_t g : groups_c) {
@@ -1876,7 +1881,7 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
       c.group_bytes = g;
       c.xcd_ranges = x;
       if ((st_ = trial(c, &ms)) != LBM_OK) break;
-      if (best < 0.0f || ms < best) best = ms, cur.group_bytes = g, cur.xcd_ranges = x;
+      if (best < 0.0f || better(ms)) best = ms, cur.group_bytes = g, cur.xcd_ranges = x;
     }
     if (st_ != LBM_OK) break;
   }
@@ -1886,14 +1891,14 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
     lbm_launch c = cur;
     c.block = bl;
     if ((st_ = trial(c, &ms)) != LBM_OK) break;
-    if (ms < best) best = ms, cur.block = bl;
+    if (better(ms)) best = ms, cur.block = bl;
   }
   for (int pc : per_cu_c) {
     if (st_ != LBM_OK || pc == start.blocks_per_cu) continue;
     lbm_launch c = cur;
     c.blocks_per_cu = pc;
     if ((st_ = trial(c, &ms)) != LBM_OK) break;
-    if (ms < best) best = ms, cur.blocks_per_cu = pc;
+    if (better(ms)) best = ms, cur.blocks_per_cu = pc;
   }
   // then the threads per tile of each size class present, one class at a time
   // (members of a class whose choice differs from the rest launch apart)
@@ -1907,7 +1912,7 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch* b, lbm_launch* out) {
       b->class_block[k] = bl;
       b->dirty = true;
       if ((st_ = trial(cur, &ms)) != LBM_OK) break;
-      if (ms < best) best = ms, keep = bl;
+      if (better(ms)) best = ms, keep = bl;
     }
     b->class_block[k] = keep;
     b->dirty = true;
