@@ -38,3 +38,16 @@ def test_the_valu_profile_names_the_kernel_it_was_taken_on():
         waves = rec["nodes"] // 64
         assert 600 <= rec["even_valu"] / waves < rec["odd_valu"] / waves <= 1200
         assert rec["valu_per_step"] == (rec["even_valu"] + rec["odd_valu"]) / 2
+
+
+def test_the_kernel_hash_ignores_comments_and_sees_code():
+    """The source hash that ties profiles to kernels drops C++ and Python
+    comments and blank lines, and nothing else."""
+    sys.path.insert(0, ROOT)
+    import bench
+    cpp = "int a = 1;  // one\n\n/* block\n comment */ int b = 2;\n"
+    assert bench._code_of("x.hpp", cpp) == bench._code_of("x.hpp", "int a = 1;\n int b = 2;")
+    assert bench._code_of("x.hpp", cpp) != bench._code_of("x.hpp", cpp.replace("2;", "3;"))
+    py = "FLAGS = ['-O3']  # optimise\n# note\n"
+    assert bench._code_of("b.py", py) == "FLAGS = ['-O3']"
+    assert bench._code_of("b.py", py) != bench._code_of("b.py", py.replace("-O3", "-O2"))
