@@ -185,7 +185,8 @@ lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t bytes, void* st
  * caller's buffer) and the handle.  NULL is accepted. */
 lbm_status lbm_destroy(lbm_lattice* h);
 
-/* Changes the stream later calls enqueue on. The caller orders the two streams. */
+/* Changes the stream later calls enqueue on. The caller orders the two streams
+ * (a Nusselt reduction started by lbm_nusselt_start is waited for here). */
 lbm_status lbm_set_stream(lbm_lattice* h, void* stream);
 
 /* Enqueues nsteps >= 0 fused time steps t -> t + nsteps.  When check_interval

@@ -751,6 +751,9 @@ extern "C" lbm_status lbm_destroy(lbm_lattice* h) {
 extern "C" lbm_status lbm_set_stream(lbm_lattice* h, void* stream) {
   if (!h) return fail(LBM_ERR_INVALID_ARG, "lattice is NULL");
   if (h->batch) return fail(LBM_ERR_INVALID_ARG, "the lattice is in a batch and uses the batch's stream");
+  // a Nusselt reduction started on the old stream is collected by waiting on
+  // the new one: let it finish first
+  if (h->nu_pending) HIP_TRY(hipStreamSynchronize(h->stream));
   h->stream = (hipStream_t)stream;
   return LBM_OK;
 }

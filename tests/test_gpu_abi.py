@@ -123,3 +123,11 @@ def test_nusselt_start_collects_the_state_it_started_on():
         assert now != ref and now[0] != 0.0
         lat.nusselt_start()
         assert lat.nusselt() == now
+        # a reduction started on one stream and collected after a stream change
+        lat.step(5)
+        later = lat.nusselt()
+        lat.nusselt_start()
+        other = torch.cuda.Stream()
+        assert lbm.library().lbm_set_stream(lat._h, ctypes.c_void_p(other.cuda_stream)) == 0
+        lat.stream = other
+        assert lat.nusselt() == later
