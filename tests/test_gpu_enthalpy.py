@@ -104,4 +104,6 @@ def test_enthalpy_lattices_refuse_temperature_queries():
         with pytest.raises(LBMError):
             lat.nusselt()
         with pytest.raises(LBMError):
+            lat.nusselt_start()
+        with pytest.raises(LBMError):
             lat.totals()
