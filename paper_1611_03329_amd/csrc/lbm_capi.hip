@@ -60,6 +60,7 @@ struct lbm_lattice {
   int pstride = 0;
   int block = 256;
   int nblocks = 0;
+  int even_lds = 0;  // dynamic LDS of the even step's launches (caps its resident blocks)
   // carve-up of the device buffer
   void* mf = nullptr;  // moving flow populations
   void* mg = nullptr;  // moving temperature populations
@@ -388,6 +389,27 @@ struct Layout {
   int pstride, nblocks, block, nfold;
 };
 
+// Resident blocks of the even step.  The even step reads and writes only the
+// node's own slots, and on a large lattice it waits on DRAM; with fewer blocks
+// in flight it streams faster: capped at two resident blocks per CU (instead
+// of the five or three its registers allow) it ran 2.3-3.0 % faster on 256^3
+// cavities (FP32 and FP64, D3Q19 and D3Q15), a 512x256x128 box and a 320^3
+// cavity, 1.2 % on a 192^3 one, and slower on a 128^3 cavity and below and on
+// the channels with inflow and outlet faces (whose even step is served partly
+// from the last-level cache); FP16 storage gained under 1 % at four blocks and
+// lost on the channel.  Dynamic LDS that the kernel never touches holds the
+// cap: 64 KiB of a CU's 160 KiB leaves room for two blocks.  The state and
+// the residuals do not depend on it.
+constexpr int kEvenCapLds = 64 * 1024;
+constexpr long long kEvenCapNodes = 1LL << 22;
+
+template <class C>
+static int even_step_lds(const lbm_params* p, const KParams<C>& k, long long nodes) {
+  const bool lean = !(k.moving || k.open_flow || k.open_heat);
+  const bool wide = p->precision == LBM_FP32 || p->precision == LBM_FP64;
+  return (p->energy != LBM_ENERGY_ENTHALPY && lean && wide && nodes >= kEvenCapNodes) ? kEvenCapLds : 0;
+}
+
 static Layout layout(const lbm_params* p) {
   Layout L;
   const long long nodes = (long long)p->nx * p->ny * p->nz;
@@ -659,6 +681,7 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   h->dev_member = base + L.member;
   fill_kparams<double>(p, &d, h->nodes, h->pstride, &h->kd);
   fill_kparams<float>(p, &d, h->nodes, h->pstride, &h->kf);
+  h->even_lds = even_step_lds(p, h->kf, h->nodes);
 
   int iso[6];
   for (int f = 0; f < 6; ++f) {
@@ -775,14 +798,16 @@ template <class Lat, class S, class C, bool ODD, bool GEN, bool SEP = false>
 static void launch_step_mode(lbm_lattice* h, const KParams<C>& kp, int mode) {
   const auto* mem = static_cast<const Member<S, C>*>(h->dev_member);
   const dim3 g(h->nblocks), b(h->block);
+  const unsigned lds = ODD ? 0u : (unsigned)h->even_lds;
   if (mode == kModePlain)
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModePlain, GEN, SEP>()), g, b, 0, h->stream, mem, 1, h->nblocks, 0);
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModePlain, GEN, SEP>()), g, b, lds, h->stream, mem, 1, h->nblocks,
+                       0);
   else if (mode == kModeSnapshot)
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeSnapshot, GEN, SEP>()), g, b, 0, h->stream, mem, 1, h->nblocks,
-                       0);
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeSnapshot, GEN, SEP>()), g, b, lds, h->stream, mem, 1,
+                       h->nblocks, 0);
   else
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeCompare, GEN, SEP>()), g, b, 0, h->stream, mem, 1, h->nblocks,
-                       0);
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeCompare, GEN, SEP>()), g, b, lds, h->stream, mem, 1,
+                       h->nblocks, 0);
 }
 
 // GEN (moving walls or open faces present) selects the kernels that compile
