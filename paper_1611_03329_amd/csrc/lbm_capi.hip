@@ -396,8 +396,8 @@ struct Layout {
 // cavities (FP32 and FP64, D3Q19 and D3Q15), a 512x256x128 box and a 320^3
 // cavity, 1.2 % on a 192^3 one, and slower on a 128^3 cavity and below and on
 // the channels with inflow and outlet faces (whose even step is served partly
-// from the last-level cache); FP16 storage gained under 1 % at four blocks and
-// lost on the channel.  Dynamic LDS that the kernel never touches holds the
+// from the last-level cache), about even at 4-5 M nodes; FP16 storage gained
+// under 1 % at four blocks and lost on the channel.  Dynamic LDS that the kernel never touches holds the
 // cap: 64 KiB of a CU's 160 KiB leaves room for two blocks.  The state and
 // the residuals do not depend on it.
 constexpr int kEvenCapLds = 64 * 1024;
@@ -798,15 +798,18 @@ template <class Lat, class S, class C, bool ODD, bool GEN, bool SEP = false>
 static void launch_step_mode(lbm_lattice* h, const KParams<C>& kp, int mode) {
   const auto* mem = static_cast<const Member<S, C>*>(h->dev_member);
   const dim3 g(h->nblocks), b(h->block);
+  // the cap of even_step_lds, for the plain even step only: the check steps'
+  // block reductions want their full residency (a capped compare step ran
+  // 728 against 632 us at 256^3)
   const unsigned lds = ODD ? 0u : (unsigned)h->even_lds;
   if (mode == kModePlain)
     hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModePlain, GEN, SEP>()), g, b, lds, h->stream, mem, 1, h->nblocks,
                        0);
   else if (mode == kModeSnapshot)
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeSnapshot, GEN, SEP>()), g, b, lds, h->stream, mem, 1,
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeSnapshot, GEN, SEP>()), g, b, 0, h->stream, mem, 1,
                        h->nblocks, 0);
   else
-    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeCompare, GEN, SEP>()), g, b, lds, h->stream, mem, 1,
+    hipLaunchKernelGGL((step_kernel<Lat, S, C, ODD, kModeCompare, GEN, SEP>()), g, b, 0, h->stream, mem, 1,
                        h->nblocks, 0);
 }
 
