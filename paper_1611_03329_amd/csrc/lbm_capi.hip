@@ -390,9 +390,13 @@ struct Layout {
 };
 
 // Resident blocks of the even step.  The even step reads and writes only the
-// node's own slots, and on a large lattice it waits on DRAM; with fewer blocks
-// in flight it streams faster: capped at two resident blocks per CU (instead
-// of the five or three its registers allow) it ran 2.3-3.0 % faster on 256^3
+// node's own slots, and on a large lattice it waits on DRAM.  With five
+// 256-thread blocks per CU some 34 MB of its lines are in flight, more than the
+// 32 MB of L2, so a line is often evicted between the node's read and its
+// write (half the L2 accesses missed); with two, every write finds its line
+// and the DRAM stalls fall by a factor of 3-4 (counters).  Capped at two
+// resident blocks per CU (instead of the five or three its registers allow)
+// it ran 2.3-3.0 % faster on 256^3
 // cavities (FP32 and FP64, D3Q19 and D3Q15), a 512x256x128 box and a 320^3
 // cavity, 1.2 % on a 192^3 one, and slower on a 128^3 cavity and below and on
 // the channels with inflow and outlet faces (whose even step is served partly
