@@ -396,22 +396,28 @@ struct Layout {
 // write (half the L2 accesses missed); with two, every write finds its line
 // and the DRAM stalls fall by a factor of 3-4 (counters).  Capped at two
 // resident blocks per CU (instead of the five or three its registers allow)
-// it ran 2.3-3.0 % faster on 256^3
-// cavities (FP32 and FP64, D3Q19 and D3Q15), a 512x256x128 box and a 320^3
-// cavity, 1.2 % on a 192^3 one, and slower on a 128^3 cavity and below and on
-// the channels with inflow and outlet faces (whose even step is served partly
-// from the last-level cache), about even at 4-5 M nodes; FP16 storage gained
-// under 1 % at four blocks and lost on the channel.  Dynamic LDS that the kernel never touches holds the
-// cap: 64 KiB of a CU's 160 KiB leaves room for two blocks.  The state and
-// the residuals do not depend on it.
+// the FP32 and FP64 even steps ran 2.3-3.0 % faster on 256^3 cavities (D3Q19
+// and D3Q15), a 512x256x128 box and a 320^3 cavity, 1.2 % on a 192^3 one,
+// about even at 4-5 M nodes, and slower on a 128^3 cavity and below and on the
+// channels with inflow and outlet faces (whose even step is served partly from
+// the last-level cache).  FP16 storage moves 68 instead of 104 bytes per node
+// and way: capped at four blocks the whole step ran 1.0-1.7 % faster on 256^3
+// (D3Q19, D3Q15) and 320^3 cavities, 0.6 % slower on 192^3, and 5 % slower on
+// the channel.  Dynamic LDS that the kernel never touches holds the cap: 64 KiB
+// of a CU's 160 KiB leaves room for two blocks, 40 KiB for four.  The state
+// and the residuals do not depend on it.
 constexpr int kEvenCapLds = 64 * 1024;
 constexpr long long kEvenCapNodes = 1LL << 22;
+constexpr int kEvenCapLdsFp16 = 40 * 1024;
+constexpr long long kEvenCapNodesFp16 = 1LL << 23;
 
 template <class C>
 static int even_step_lds(const lbm_params* p, const KParams<C>& k, long long nodes) {
   const bool lean = !(k.moving || k.open_flow || k.open_heat);
-  const bool wide = p->precision == LBM_FP32 || p->precision == LBM_FP64;
-  return (p->energy != LBM_ENERGY_ENTHALPY && lean && wide && nodes >= kEvenCapNodes) ? kEvenCapLds : 0;
+  if (p->energy == LBM_ENERGY_ENTHALPY || !lean) return 0;
+  if ((p->precision == LBM_FP32 || p->precision == LBM_FP64) && nodes >= kEvenCapNodes) return kEvenCapLds;
+  if (p->precision == LBM_FP16_STORAGE && nodes >= kEvenCapNodesFp16) return kEvenCapLdsFp16;
+  return 0;
 }
 
 static Layout layout(const lbm_params* p) {
