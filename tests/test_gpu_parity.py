@@ -346,6 +346,23 @@ def test_cavity256_fp32_two_steps_match_oracle():
         assert err <= 1e-5, (k, err)
 
 
+def test_cavity256_fp64_four_steps_match_oracle():
+    """The 256^3 cavity in FP64 (128-thread blocks, the even step's launches
+    capped at two resident blocks per CU) for two even and two odd steps
+    against the oracle, fields to 1e-10."""
+    wl = lbm_inputs.config_cavity_fp32()
+    _say("case cavity256 fp64 full size, 4 steps (oracle on the host)")
+    with oracle.Oracle(wl) as o:
+        o.step(4)
+        ref = o.fields()
+    with Lattice(wl, "fp64", check_interval=100) as lat:
+        lat.step(4)
+        fl = _gpu_fields(lat)
+    for k, err in _field_errors(fl, ref).items():
+        _say(f"  {k}: rel err {err:.3e}")
+        assert err <= 1e-10, (k, err)
+
+
 @pytest.mark.parametrize("q", [19, 15])
 def test_fp64_128_thread_blocks_match_oracle(q):
     """FP64 flow lattices of 2^20 nodes or more step in 128-thread blocks: a
