@@ -413,3 +413,24 @@ def test_span_residual_matches_oracle():
             out.append(r[0])
             lat.close()
     assert out[0] == out[1]
+
+
+@pytest.mark.parametrize("prec,shape", [("fp32", (256, 128, 128)), ("fp64", (256, 128, 128)),
+                                        ("fp16", (256, 256, 128))])
+def test_capped_even_step_changes_no_state(prec, shape):
+    """A lean lattice large enough for the even step's residency cap (lbm_step
+    launches its plain even steps with two resident blocks per CU, four for
+    FP16 storage) ends bit for bit where its one-member batch (launches
+    uncapped) does, over steps of both parities and a residual check."""
+    wl = lbm_inputs.cavity(shape, porosity=0.5, darcy=1e-3, rayleigh=1e5, seed=17)
+    _say(f"case capped even step vs batch launch {prec} {shape}")
+    solo = _make(wl, None, prec, 4)
+    solo.step(9)
+    with Batch(check_interval=4) as b:
+        mem = _make(wl, None, prec, 4)
+        b.add(mem)
+        b.step(9)
+        assert _same(solo, mem)
+        b.remove(mem)
+    mem.close()
+    solo.close()
