@@ -9,7 +9,7 @@ the timed region starts.
 Prints ONE JSON line: MLUPS (whole job), the roofline of the step kernel
 (algorithmic bytes = 2 x 26 populations x 4 B = 208 B per node per step) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
---precision fp16 runs the same cavity with FP16 flow populations (136 B per
+--precision fp16 runs the same cavity with FP16 flow populations (132 B per
 node per step).  Like the FP32 step it is bound by HBM; the line adds its VALU
 issue rate beside the bytes (wave64 VALU instructions per CU per clock at
 2.4 GHz, the instruction count per step taken from the committed counter
@@ -370,7 +370,7 @@ def bench_channel(args) -> int:
     torch.cuda.set_device(0)
     wl = lbm_inputs.config_channel()
     runs = {}
-    for prec, bpn in (("fp32", 2 * 22 * 4), ("fp16", 2 * (14 * 2 + 8 * 4))):
+    for prec, bpn in (("fp32", 2 * 22 * 4), ("fp16", 2 * (15 * 2 + 7 * 4))):
         lat = Lattice(wl, prec, check_interval=args.check_interval)
         nodes = lat.nodes
         ms = _time_steps(lat, args.warmup, args.steps)
@@ -684,7 +684,7 @@ def main(argv=None) -> int:
           f"({checks} checks timed), Nu_hot {nu[0]:.5f}", file=sys.stderr, flush=True)
 
     fp16 = args.precision == "fp16"
-    bytes_per_node = 2 * (18 * 2 + 8 * 4) if fp16 else 2 * (19 + 7) * 4
+    bytes_per_node = 2 * (19 * 2 + 7 * 4) if fp16 else 2 * (19 + 7) * 4
     achieved = bytes_per_node * nodes / (ms_per_step / 1e3) / 1e9
     traffic = None if fp16 else traffic_from_profiles(nodes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",

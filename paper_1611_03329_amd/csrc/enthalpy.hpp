@@ -84,7 +84,7 @@ __device__ __forceinline__ void collide_enthalpy(const EnthalpyConsts<C>& ec, C 
 // gather with the static thermal wall rules).  g_0 sits in the second rest plane.
 template <bool ODD, class S, class C>
 __device__ __forceinline__ void gather_g(const KParams<C>& kp, const S& sto, int n, const Nbr& nb, C (&g)[7]) {
-  g[0] = ld_rs<S, C>(sto, rslot(1, (uint32_t)n));
+  g[0] = ld_g0<S, C>(sto, (uint32_t)n);
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if constexpr (!ODD) {
@@ -104,7 +104,7 @@ __device__ __forceinline__ void gather_g(const KParams<C>& kp, const S& sto, int
 
 template <bool ODD, class S, class C>
 __device__ __forceinline__ void scatter_g(const KParams<C>& kp, const S& sto, int n, const Nbr& nb, const C (&g)[7]) {
-  st_rs<S, C>(sto, rslot(1, (uint32_t)n), g[0]);
+  st_g0<S, C>(sto, (uint32_t)n, g[0]);
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int ko = D3Q7::opp(k);
@@ -147,7 +147,7 @@ template <class S, class C>
 __global__ void __launch_bounds__(kMaxBlock) k_init_enthalpy(const KParams<C> kp, const S sto, double g0, double gk) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
-  st_rs<S, C>(sto, rslot(1, (uint32_t)n), C(g0));
+  st_g0<S, C>(sto, (uint32_t)n, C(g0));
 #pragma unroll
   for (int k = 1; k < 7; ++k) st_mg<S, C>(sto, gslot(k, (uint32_t)n), C(gk));
 }
@@ -190,7 +190,7 @@ template <class S, class C>
 __global__ void __launch_bounds__(kMaxBlock) k_set_g(const KParams<C> kp, const S sto, const double* g_in) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= kp.n) return;
-  st_rs<S, C>(sto, rslot(1, (uint32_t)n), C(g_in[n]));
+  st_g0<S, C>(sto, (uint32_t)n, C(g_in[n]));
 #pragma unroll
   for (int k = 1; k < 7; ++k) st_mg<S, C>(sto, gslot(k, (uint32_t)n), C(g_in[(size_t)k * kp.n + n]));
 }

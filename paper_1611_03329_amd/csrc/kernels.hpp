@@ -79,10 +79,10 @@ __device__ __forceinline__ C ld_raw(const S* base, uint32_t e) {
 // Population storage in three regions: the moving flow populations f_1..f_{Q-1}
 // (type Mf), the moving temperature populations g_1..g_6 (type Mg) and the two
 // rest populations f_0, g_0 (type Rs), which never leave their node.  With FP16
-// storage only the moving flow populations are FP16: the heat flux is carried
-// by the difference of opposite g populations, far below FP16's resolution of
-// each of them, and the rest populations change only through the collision, by
-// amounts FP16 would round away.
+// storage the flow populations are FP16, f_0 too, in a plane of its own (r0;
+// the rest region then holds g_0 alone); the temperature populations stay
+// FP32: the heat flux is carried by the difference of opposite g populations,
+// far below FP16's resolution of each of them.
 template <class Mf, class Mg, class Rs>
 struct Store {
   using MoveF = Mf;
@@ -91,6 +91,7 @@ struct Store {
   Mf* mf;
   Mg* mg;
   Rs* rs;
+  Mf* r0;  // f_0 with FP16 flow storage, else unused
 };
 
 // Each region stores its populations in tiles of kTile nodes: the kTile values
@@ -105,12 +106,17 @@ template <uint32_t P>
 __device__ __forceinline__ uint32_t tiled(uint32_t pop, uint32_t n) {
   return (((n >> kTileShift) * P + pop) << kTileShift) | (n & (kTile - 1u));
 }
-// element of moving flow population i >= 1, moving temperature population
-// k >= 1 and rest population r (0: f_0, 1: g_0) of node n
+// element of moving flow population i >= 1 and moving temperature population
+// k >= 1 of node n
 template <class Lat>
 __device__ __forceinline__ uint32_t fslot(int i, uint32_t n) { return tiled<(uint32_t)(Lat::Q - 1)>((uint32_t)(i - 1), n); }
 __device__ __forceinline__ uint32_t gslot(int k, uint32_t n) { return tiled<6u>((uint32_t)(k - 1), n); }
-__device__ __forceinline__ uint32_t rslot(int r, uint32_t n) { return tiled<2u>((uint32_t)r, n); }
+// The rest populations f_0 and g_0 share the rest region, tiled in pairs,
+// unless the flow populations are FP16 (f_0 in r0, g_0 alone in the rest region).
+template <class S>
+constexpr bool kHalfRest = std::is_same<typename S::MoveF, _Float16>::value;
+template <class S>
+__device__ __forceinline__ uint32_t g0slot(uint32_t n) { return kHalfRest<S> ? n : tiled<2u>(1u, n); }
 
 template <class S, class C>
 __device__ __forceinline__ C ld_mf(const S& s, uint32_t e) { return ld<typename S::MoveF, C>(s.mf, e); }
@@ -123,13 +129,25 @@ __device__ __forceinline__ C ld_mf_as(const S& s, uint32_t e) {
 template <class S, class C>
 __device__ __forceinline__ C ld_mg(const S& s, uint32_t e) { return ld<typename S::MoveG, C>(s.mg, e); }
 template <class S, class C>
-__device__ __forceinline__ C ld_rs(const S& s, uint32_t e) { return ld<typename S::Rest, C>(s.rs, e); }
+__device__ __forceinline__ C ld_g0(const S& s, uint32_t n) { return ld<typename S::Rest, C>(s.rs, g0slot<S>(n)); }
+// f_0 as the step carries it: times kFlowScale<S> (RAW) or true
+template <bool RAW, class S, class C>
+__device__ __forceinline__ C ld_f0_as(const S& s, uint32_t n) {
+  if constexpr (kHalfRest<S>) return RAW ? ld_raw<_Float16, C>(s.r0, n) : ld<_Float16, C>(s.r0, n);
+  else return ld<typename S::Rest, C>(s.rs, tiled<2u>(0u, n));
+}
 template <class S, class C>
 __device__ __forceinline__ void st_mf(const S& s, uint32_t e, C v) { st<typename S::MoveF, C>(s.mf, e, v); }
 template <class S, class C>
 __device__ __forceinline__ void st_mg(const S& s, uint32_t e, C v) { st<typename S::MoveG, C>(s.mg, e, v); }
 template <class S, class C>
-__device__ __forceinline__ void st_rs(const S& s, uint32_t e, C v) { st<typename S::Rest, C>(s.rs, e, v); }
+__device__ __forceinline__ void st_g0(const S& s, uint32_t n, C v) { st<typename S::Rest, C>(s.rs, g0slot<S>(n), v); }
+// f_0 given as true value, rounded to nearest (initial and caller-given states)
+template <class S, class C>
+__device__ __forceinline__ void st_f0(const S& s, uint32_t n, C v) {
+  if constexpr (kHalfRest<S>) st<_Float16, C>(s.r0, n, v);
+  else st<typename S::Rest, C>(s.rs, tiled<2u>(0u, n), v);
+}
 
 // FP16 flow storage rounds stochastically: a value goes to one of its two
 // neighbouring FP16 numbers with probability falling linearly with the
@@ -175,6 +193,20 @@ __device__ __forceinline__ void st_mf_r(const S& s, uint32_t e, C v, uint32_t r1
   } else {
     (void)r13;
     st_mf<S, C>(s, e, v);
+  }
+}
+
+// Store of f_0 given as the step carries it (RAW: times kFlowScale<S>; else
+// true); with FP16 storage r13 drives the rounding, as for st_mf_r.
+template <bool RAW, class S, class C>
+__device__ __forceinline__ void st_f0_r(const S& s, uint32_t n, C v, uint32_t r13) {
+  if constexpr (kHalfRest<S>) {
+    LBM_GLOBAL char* b = (LBM_GLOBAL char*)s.r0;
+    const float f = RAW ? (float)v : (float)v * kHalfScale;
+    *(LBM_GLOBAL _Float16*)(b + n * 2u) = half_sr(f, r13);
+  } else {
+    (void)r13;
+    st<typename S::Rest, C>(s.rs, tiled<2u>(0u, n), v);
   }
 }
 
@@ -435,7 +467,7 @@ template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false, boo
 __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                        C (&h)[Lat::Q], C (&p)[7]) {
   constexpr int SC = RAW ? kFlowScale<S> : 1;
-  h[0] = ld_rs<S, C>(sto, rslot(0, (uint32_t)n)) * C(SC);
+  h[0] = ld_f0_as<RAW, S, C>(sto, (uint32_t)n);
   const uint32_t f1 = fslot<Lat>(1, (uint32_t)n);
   int td[3][2];
   if constexpr (ODD && SEP) tile_deltas<Lat>(nb, n, f1, td);
@@ -461,7 +493,7 @@ __device__ __forceinline__ void gather(const KParams<C>& kp, const S& sto, int n
     }
   });
   if constexpr (GEN && ODD) gather_walls<Lat, SC, C>(kp, nb, h);
-  p[0] = ld_rs<S, C>(sto, rslot(1, (uint32_t)n));
+  p[0] = ld_g0<S, C>(sto, (uint32_t)n);
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     if constexpr (!ODD) {
@@ -489,12 +521,12 @@ template <class Lat, bool ODD, bool GEN, class S, class C, bool SEP = false, boo
 __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int n, const Nbr& nb,
                                         const C (&h)[Lat::Q], const C (&p)[7], const Macro<C>& M, uint32_t seed) {
   constexpr int SC = RAW ? kFlowScale<S> : 1;
-  st_rs<S, C>(sto, rslot(0, (uint32_t)n), h[0] * C(1.0 / SC));
   // random bits for the stochastic FP16 rounding: one hashed word per node and
   // step, and for population i the top 13 bits of that word plus i times the
   // golden-ratio constant (a Weyl sequence): each population's bits are
   // uniform, and the node's populations take evenly spread rotations of them
   const uint32_t rnd = kStochastic<S> ? mix32(seed + (uint32_t)n) : 0u;
+  st_f0_r<RAW, S, C>(sto, (uint32_t)n, h[0], rnd >> 19);
   const uint32_t f1 = fslot<Lat>(1, (uint32_t)n);
   int td[3][2];
   if constexpr (ODD && SEP) tile_deltas<Lat>(nb, n, f1, td);
@@ -519,7 +551,7 @@ __device__ __forceinline__ void scatter(const KParams<C>& kp, const S& sto, int 
       st_mf_r<RAW, S, C>(sto, e, h[i], r);
     }
   });
-  st_rs<S, C>(sto, rslot(1, (uint32_t)n), p[0]);
+  st_g0<S, C>(sto, (uint32_t)n, p[0]);
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int ko = D3Q7::opp(k);
@@ -774,13 +806,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_init(const KParams<C> kp, const I
     constexpr int i = decltype(I)::value;
     const double eu = Lat::e(0, i) * ia.u[0] + Lat::e(1, i) * ia.u[1] + Lat::e(2, i) * ia.u[2];
     const double v = weight<Lat, i>() * (3.0 * eu + 4.5 * eu * eu / phi - 1.5 * uu / phi);
-    if constexpr (i == 0) st_rs<S, C>(state, rslot(0, (uint32_t)n), C(v));
+    if constexpr (i == 0) st_f0<S, C>(state, (uint32_t)n, C(v));
     else st_mf<S, C>(state, fslot<Lat>(i, (uint32_t)n), C(v));
   });
   const double dsT = (double)kp.sigma * (T - (double)kp.T_ref);
   const double vp = (double)kp.varpi;
   const double csT2 = vp / 3.0;
-  st_rs<S, C>(state, rslot(1, (uint32_t)n), C((1.0 - vp) * dsT));
+  st_g0<S, C>(state, (uint32_t)n, C((1.0 - vp) * dsT));
   static_for<1, 7>([&](auto K) {
     constexpr int k = decltype(K)::value;
     const double eu = D3Q7::e(0, k) * ia.u[0] + D3Q7::e(1, k) * ia.u[1] + D3Q7::e(2, k) * ia.u[2];
@@ -939,14 +971,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_set_state(const KParams<C> kp, co
   static_for<0, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     const C v = C(f_in[(size_t)i * kp.n + n] - weight<Lat, i>());
-    if constexpr (i == 0) st_rs<S, C>(state, rslot(0, (uint32_t)n), v);
+    if constexpr (i == 0) st_f0<S, C>(state, (uint32_t)n, v);
     else st_mf<S, C>(state, fslot<Lat>(i, (uint32_t)n), v);
   });
   const double vp = (double)kp.varpi, sT = (double)kp.sigma * (double)kp.T_ref;
   for (int k = 0; k < 7; ++k) {
     const double om = k == 0 ? 1.0 - vp : vp / 6.0;
     const C v = C(g_in[(size_t)k * kp.n + n] - om * sT);
-    if (k == 0) st_rs<S, C>(state, rslot(1, (uint32_t)n), v);
+    if (k == 0) st_g0<S, C>(state, (uint32_t)n, v);
     else st_mg<S, C>(state, gslot(k, (uint32_t)n), v);
   }
 }
@@ -967,10 +999,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_transfer(const KParams<CS> kps, c
   gather<Lat, ODD, true, SS, CS>(kps, src, n, nb, h, p);
   static_for<0, Lat::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    if constexpr (i == 0) st_rs<SD, CD>(dst, rslot(0, (uint32_t)n), (CD)h[0]);
+    if constexpr (i == 0) st_f0<SD, CD>(dst, (uint32_t)n, (CD)h[0]);
     else st_mf<SD, CD>(dst, fslot<Lat>(i, (uint32_t)n), (CD)h[i]);
   });
-  st_rs<SD, CD>(dst, rslot(1, (uint32_t)n), (CD)p[0]);
+  st_g0<SD, CD>(dst, (uint32_t)n, (CD)p[0]);
 #pragma unroll
   for (int k = 1; k < 7; ++k) st_mg<SD, CD>(dst, gslot(k, (uint32_t)n), (CD)p[k]);
 }

@@ -64,7 +64,8 @@ struct lbm_lattice {
   // carve-up of the device buffer
   void* mf = nullptr;  // moving flow populations
   void* mg = nullptr;  // moving temperature populations
-  void* rs = nullptr;  // rest populations
+  void* rs = nullptr;  // rest populations (g_0 alone with FP16 flow storage)
+  void* r0 = nullptr;  // f_0 with FP16 flow storage
   void* snap = nullptr;
   double* part = nullptr;
   double* part2 = nullptr;  // first-stage fold of part
@@ -385,7 +386,7 @@ static_assert(sizeof(Member<Store<double, double, double>, double>) <= kMemberBy
 static_assert(sizeof(Member<Store<float, float, float>, float>) <= kMemberBytes, "member table entry too large");
 
 struct Layout {
-  size_t mf, mg, rs, snap, part, part2, res, clk, iso, member, total;
+  size_t mf, mg, rs, r0, snap, part, part2, res, clk, iso, member, total;
   int pstride, nblocks, block, nfold;
 };
 
@@ -440,8 +441,13 @@ static Layout layout(const lbm_params* p) {
   off += enth ? 0 : align_up((size_t)(p->lattice - 1) * L.pstride * s, 256);
   L.mg = off;
   off += align_up((size_t)6 * L.pstride * c, 256);
+  // rest populations: f_0 and g_0 in the compute type; with FP16 flow storage
+  // g_0 alone there and f_0 in an FP16 plane of its own (r0)
+  const bool half = p->precision == LBM_FP16_STORAGE && !enth;
   L.rs = off;
-  off += align_up((size_t)2 * L.pstride * c, 256);
+  off += align_up((size_t)(half ? 1 : 2) * L.pstride * c, 256);
+  L.r0 = off;
+  off += half ? align_up((size_t)L.pstride * 2, 256) : 0;
   L.snap = off;
   off += enth ? 0 : align_up((size_t)4 * nodes * c, 256);
   L.part = off;
@@ -495,6 +501,7 @@ static S make_store(const lbm_lattice* h) {
   s.mf = static_cast<typename S::MoveF*>(h->mf);
   s.mg = static_cast<typename S::MoveG*>(h->mg);
   s.rs = static_cast<typename S::Rest*>(h->rs);
+  s.r0 = static_cast<typename S::MoveF*>(h->r0);
   return s;
 }
 
@@ -681,6 +688,7 @@ extern "C" lbm_status lbm_create(const lbm_params* p, void* dev_buf, size_t byte
   h->mf = base + L.mf;
   h->mg = base + L.mg;
   h->rs = base + L.rs;
+  h->r0 = base + L.r0;
   h->snap = base + L.snap;
   h->part = reinterpret_cast<double*>(base + L.part);
   h->part2 = reinterpret_cast<double*>(base + L.part2);

@@ -119,9 +119,9 @@ def test_required_bytes_layout():
     assert 26 * n * 4 + 4 * n * 4 <= b32 < 26 * n * 4 + 4 * n * 4 + (1 << 20)
     b15 = lbm.required_bytes(lbm.make_params(lbm_inputs.cavity(32, lattice=15), "fp32"))
     assert b15 < b32
-    # FP16 storage: 18 moving f in FP16, 6 moving g and 2 rest populations in FP32
+    # FP16 storage: the 19 flow populations in FP16, the 7 temperature populations in FP32
     b16 = lbm.required_bytes(lbm.make_params(lbm_inputs.cavity(32), "fp16"))
-    assert (18 * 2 + 8 * 4) * n + 4 * n * 4 <= b16 < (18 * 2 + 8 * 4) * n + 4 * n * 4 + (1 << 20)
+    assert (19 * 2 + 7 * 4) * n + 4 * n * 4 <= b16 < (19 * 2 + 7 * 4) * n + 4 * n * 4 + (1 << 20)
 
 
 def test_size_limits_are_exact():
