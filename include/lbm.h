@@ -79,7 +79,7 @@ typedef enum {
 typedef enum {
   LBM_FP64 = 0,        /* populations stored and computed in FP64 */
   LBM_FP32 = 1,        /* populations stored and computed in FP32 */
-  LBM_FP16_STORAGE = 2 /* moving flow populations stored in FP16; temperature and rest
+  LBM_FP16_STORAGE = 2 /* flow populations (the rest one too) stored in FP16; temperature
                           populations in FP32; arithmetic in FP32.  The FP16 stores round
                           stochastically (zero-mean error) with random bits hashed from the
                           lattice's step count, node and population: reproducible runs */

@@ -93,7 +93,7 @@ class Server:
     precision "fp32": every solve in FP32 storage, checked every
     `check_interval` steps with the one-step residual.
 
-    precision "fp16": a solve starts in FP16 storage (136 instead of 208 bytes
+    precision "fp16": a solve starts in FP16 storage (132 instead of 208 bytes
     per node and step).  FP16 rounding of the stored populations puts a floor
     under the one-step residual (about 2e-4 to 7e-3 relative on the cavity
     workloads), reached within the first few thousand steps, after the fast
